@@ -1,0 +1,131 @@
+/*
+ * fofse.h - C ABI of the MI355X (gfx950) implementation of fast orthogonality
+ * deficiency compensated frequency selective extrapolation (FOFSE).
+ *
+ * Seiler & Kaup, "Fast orthogonality deficiency compensation for improved
+ * frequency selective image extrapolation".  Problem statement (Section 2,
+ * Fig. 1): an area L = A u B of M x N samples; the samples of f are known on
+ * the support area A, and the model g (eq. 1) built over L by K iterations
+ * (eqs. 2-9 with the constant compensation of eq. 14) is the estimate of f on
+ * the missing area B.  Weighting w = rho on A, 0 elsewhere (eq. 4), with the
+ * isotropic model rho = rho_hat ** dist(centre) (eq. 15).  Basis functions:
+ * the T x T two-dimensional DFT (Results section), handled entirely in the
+ * transform domain.
+ *
+ * Conventions shared by every entry point:
+ *   - "device" pointers are HIP device memory of the plan's device; "host"
+ *     pointers are ordinary host memory.  The library never frees caller memory.
+ *   - All calls taking a stream are asynchronous on that stream (a hipStream_t
+ *     passed as void*; NULL = the null stream).  Argument errors are detected on
+ *     the host, return synchronously and enqueue nothing.
+ *   - Data-dependent per-block problems never abort a batch: they are reported
+ *     in the per-block status word and the block's outputs are zero.
+ *   - A plan may be used from one host thread and one stream at a time.
+ */
+#ifndef FOFSE_H
+#define FOFSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fofse_plan_s* fofse_plan;   /* opaque; owned by the library */
+
+typedef enum {
+    FOFSE_OK = 0,
+    FOFSE_ERR_ARG = 1,          /* invalid argument (NULL, size, range)       */
+    FOFSE_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. an FFT size)     */
+    FOFSE_ERR_NOMEM = 3,        /* device allocation failed (create only)     */
+    FOFSE_ERR_DEVICE = 4        /* a HIP call or a kernel launch failed       */
+} fofse_status;
+
+/* Per-block status bits written to d_status (0 = block processed normally). */
+#define FOFSE_BLOCK_NO_SUPPORT   1  /* sum of weights W0 <= 0 (no usable sample)  */
+#define FOFSE_BLOCK_NONFINITE    2  /* a known sample is NaN or infinite          */
+#define FOFSE_BLOCK_BAD_PARAM    4  /* rho_hat not in (0,1] or gamma not in (0,1] */
+
+/*
+ * Geometry of one class of areas (Fig. 1).
+ *   area_h, area_w : M, N, the area size (1 <= M, N <= fft_size).  The isotropic
+ *                    model is centred at ((M-1)/2, (N-1)/2) (eq. 15).
+ *   fft_size       : T, the DFT size (the paper's FFT size, Section 3).
+ *                    Supported: 32 and 64.
+ *   iterations     : K >= 0, the number of iterations (the paper's I, Table 1),
+ *                    at most 4096.
+ *   target_mask    : host, M*N bytes row-major, non-zero on the missing area B.
+ *                    Copied at creation; at least one non-zero byte.
+ */
+typedef struct {
+    int32_t area_h;
+    int32_t area_w;
+    int32_t fft_size;
+    int32_t iterations;
+    const uint8_t* target_mask;
+} fofse_geometry;
+
+/*
+ * Create a plan for one geometry on HIP device `device`.  Uploads the target
+ * pixel list and the DFT twiddle table to the device (the plan owns them).
+ * Returns FOFSE_ERR_ARG for an invalid geometry or NULL out, FOFSE_ERR_UNSUPPORTED
+ * for an FFT size that is not built, FOFSE_ERR_NOMEM / FOFSE_ERR_DEVICE on HIP
+ * failures.  *out is set only on FOFSE_OK.
+ */
+fofse_status fofse_create(const fofse_geometry* geometry, int32_t device,
+                          fofse_plan* out);
+
+/* Number of samples of the missing area B of the plan's geometry (0 if NULL). */
+int32_t fofse_target_count(fofse_plan plan);
+
+/*
+ * Extrapolate n_blocks areas of the plan's geometry (Sections 2 and 3).
+ *
+ * For every block b, K iterations of FOFSE run in the DFT domain: the weighted
+ * known samples w*f are transformed once (eqs. 7, 8); each iteration picks the
+ * conjugate class with the largest |R_w| (eq. 9), estimates its coefficient
+ * c = gamma * R_w[u] / W0 (eqs. 5 and 14), adds c phi_u + conj(c) phi_-u to the
+ * model (eq. 2) and removes it from the weighted residual spectrum via the
+ * shifted transform of w (eq. 3); the model is synthesised on B (eq. 1).
+ * Arithmetic is IEEE double precision on the device.
+ *
+ *   d_areas      device float [n_blocks][M*N], row-major samples of f.  Samples
+ *                outside A are ignored (they may hold anything finite or not).
+ *   d_known      device uint8 [n_blocks][M*N], non-zero where the sample is in
+ *                the support area A; bytes on B are ignored (B is never known).
+ *                NULL: every block's A is the complement of B.
+ *   d_rho_gamma  device double [2] = {rho_hat, gamma}, read when the kernel
+ *                runs (so a captured graph sees updated values).  rho_hat in
+ *                (0,1], gamma in (0,1]; otherwise every block reports
+ *                FOFSE_BLOCK_BAD_PARAM.
+ *   d_out        device float [n_blocks][nB] with nB = fofse_target_count():
+ *                g on the samples of B in row-major order of the area.
+ *   d_sel        device int32 [n_blocks][K] or NULL: canonical key u*T+v of the
+ *                class selected in each iteration (u,v with v in [0,T/2], and
+ *                u in [0,T/2] when v is 0 or T/2).
+ *   d_coef       device double [n_blocks][K][2] or NULL: coefficient c (re, im)
+ *                added for that class (im = 0 for a self-conjugate class).
+ *   d_status     device int32 [n_blocks] or NULL: FOFSE_BLOCK_* bits.
+ *   stream       hipStream_t (as void*), NULL for the null stream.
+ *
+ * Returns FOFSE_ERR_ARG (NULL plan or required pointer, n_blocks < 0),
+ * FOFSE_ERR_DEVICE if the launch fails, FOFSE_OK otherwise.  n_blocks == 0 is
+ * a no-op.
+ */
+fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
+                                     const float* d_areas, const uint8_t* d_known,
+                                     const double* d_rho_gamma, float* d_out,
+                                     int32_t* d_sel, double* d_coef,
+                                     int32_t* d_status, void* stream);
+
+/* Release the plan and its device memory.  NULL is ignored. */
+void fofse_destroy(fofse_plan plan);
+
+/* Static string for a status code (never NULL). */
+const char* fofse_status_str(fofse_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOFSE_H */

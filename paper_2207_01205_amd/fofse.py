@@ -1,0 +1,179 @@
+"""ctypes binding of the FOFSE C ABI (include/fofse.h).
+
+Argument marshalling only: every step of the extrapolation runs in the HIP
+kernels of libfofse.so.  PyTorch supplies device memory and the current stream.
+There is no fallback: if the library is not built or cannot be loaded, every
+call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfofse.so")
+
+FOFSE_OK = 0
+FOFSE_ERR_ARG = 1
+FOFSE_ERR_UNSUPPORTED = 2
+FOFSE_ERR_NOMEM = 3
+FOFSE_ERR_DEVICE = 4
+
+FOFSE_BLOCK_NO_SUPPORT = 1
+FOFSE_BLOCK_NONFINITE = 2
+FOFSE_BLOCK_BAD_PARAM = 4
+
+EXPORTED = ("fofse_create", "fofse_target_count", "fofse_extrapolate_batch",
+            "fofse_destroy", "fofse_status_str")
+
+
+class FofseError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {fofse_status_str(status)} ({status})")
+        self.status = status
+
+
+class fofse_geometry(ctypes.Structure):
+    _fields_ = [("area_h", ctypes.c_int32), ("area_w", ctypes.c_int32),
+                ("fft_size", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("target_mask", ctypes.POINTER(ctypes.c_uint8))]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfofse.so (once) and declare the signatures of include/fofse.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
+                           "or python -m paper_2207_01205_amd.build")
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.fofse_create.argtypes = [ctypes.POINTER(fofse_geometry), ctypes.c_int32, ctypes.POINTER(vp)]
+    L.fofse_create.restype = ctypes.c_int
+    L.fofse_target_count.argtypes = [vp]
+    L.fofse_target_count.restype = ctypes.c_int32
+    L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fofse_extrapolate_batch.restype = ctypes.c_int
+    L.fofse_destroy.argtypes = [vp]
+    L.fofse_destroy.restype = None
+    L.fofse_status_str.argtypes = [ctypes.c_int]
+    L.fofse_status_str.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+# --- one Python function per C entry point (same names) --------------------
+
+def fofse_status_str(status: int) -> str:
+    return load_library().fofse_status_str(int(status)).decode()
+
+
+def fofse_create(area_h: int, area_w: int, fft_size: int, iterations: int,
+                 target_mask, device: int = 0) -> int:
+    """Returns the opaque plan handle (an int); raises FofseError."""
+    L = load_library()
+    tm = np.ascontiguousarray(np.asarray(target_mask, dtype=np.uint8).reshape(-1))
+    if tm.size != area_h * area_w:
+        raise ValueError("target_mask must hold area_h * area_w bytes")
+    g = fofse_geometry(area_h, area_w, fft_size, iterations,
+                       tm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    out = ctypes.c_void_p()
+    st = L.fofse_create(ctypes.byref(g), int(device), ctypes.byref(out))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_create")
+    return out.value
+
+
+def fofse_target_count(plan: int) -> int:
+    return int(load_library().fofse_target_count(plan))
+
+
+def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int,
+                            d_rho_gamma: int, d_out: int, d_sel: int, d_coef: int,
+                            d_status: int, stream: int) -> None:
+    """Raw call with device addresses (ints, 0 for NULL); raises FofseError."""
+    st = load_library().fofse_extrapolate_batch(plan, int(n_blocks), d_areas or None,
+                                                d_known or None, d_rho_gamma or None,
+                                                d_out or None, d_sel or None, d_coef or None,
+                                                d_status or None, stream or None)
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_extrapolate_batch")
+
+
+def fofse_destroy(plan: int) -> None:
+    load_library().fofse_destroy(plan)
+
+
+# --- torch convenience wrapper ---------------------------------------------
+
+class Plan:
+    """A geometry (area M x N, FFT size T, K iterations, missing area B) bound
+    to one device.  Tensors are passed by address to the C ABI."""
+
+    def __init__(self, area_h: int, area_w: int, fft_size: int, iterations: int,
+                 target_mask, device: int = 0):
+        self.M, self.N, self.T, self.K = int(area_h), int(area_w), int(fft_size), int(iterations)
+        self.device = int(device)
+        self.target_mask = np.asarray(target_mask, dtype=np.uint8).reshape(self.M, self.N)
+        self.handle = fofse_create(self.M, self.N, self.T, self.K, self.target_mask, self.device)
+        self.nB = fofse_target_count(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fofse_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def extrapolate(self, areas, rho_gamma, known=None, out=None, record: bool = False,
+                    status: bool = True, stream=None):
+        """areas: cuda float32 [n, M, N]; rho_gamma: cuda float64 [2];
+        known: cuda uint8 [n, M, N] or None.  Returns (out [n, nB] float32,
+        sel [n, K] int32 or None, coef [n, K, 2] float64 or None,
+        status [n] int32 or None); all on the device, enqueued on ``stream``
+        (default: torch's current stream)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = int(areas.shape[0])
+        _check(areas, torch.float32, (n, self.M, self.N), dev, "areas")
+        _check(rho_gamma, torch.float64, (2,), dev, "rho_gamma")
+        if known is not None:
+            _check(known, torch.uint8, (n, self.M, self.N), dev, "known")
+        if out is None:
+            out = torch.empty((n, self.nB), dtype=torch.float32, device=dev)
+        else:
+            _check(out, torch.float32, (n, self.nB), dev, "out")
+        sel = coef = st = None
+        if record:
+            sel = torch.empty((n, self.K), dtype=torch.int32, device=dev)
+            coef = torch.empty((n, self.K, 2), dtype=torch.float64, device=dev)
+        if status:
+            st = torch.empty((n,), dtype=torch.int32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        fofse_extrapolate_batch(self.handle, n, areas.data_ptr(),
+                                known.data_ptr() if known is not None else 0,
+                                rho_gamma.data_ptr(), out.data_ptr(),
+                                sel.data_ptr() if sel is not None else 0,
+                                coef.data_ptr() if coef is not None else 0,
+                                st.data_ptr() if st is not None else 0,
+                                stream.cuda_stream)
+        return out, sel, coef, st
+
+
+def _check(t, dtype, shape, dev, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or t.device != dev or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on {dev}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
