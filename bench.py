@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""FOFSE forward benchmark on one MI355X.
+
+Workload: 1080p frame concealment (the paper's block-loss concealment setting:
+16x16 lost blocks, 16-pixel support frame -> 48x48 areas, 64x64 DFT, rho_hat
+0.8, gamma 0.5, K = 200 iterations), on seeded synthetic 8-bit frames with 10 %
+of the 120 x 67 full macroblocks lost (804 blocks per frame).  One step = one
+forward pass (one launch) over a batch of ``--frames`` frames, inputs resident
+in HBM.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+T, K, RHO, GAMMA, AREA = 64, 200, 0.8, 0.5, 48
+FP64_VECTOR_PEAK = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
+
+
+def flops_per_block(T: int, K: int) -> float:
+    """Algorithmic FLOP of one block: per iteration 19 per conjugate class
+    (|R|^2: 3, two complex multiply-adds: 16) over T^2/2 + 2 classes, plus two
+    T x T real FFTs at 2.5 T^2 log2(T^2) each (forward transform, synthesis)."""
+    classes = T * T // 2 + 2
+    return K * 19.0 * classes + 2 * 2.5 * T * T * np.log2(T * T)
+
+
+def _frame(i):
+    from paper_2207_01205_amd import synth
+    a = synth.frame_concealment(i, 1000 + i)
+    return a.areas, a.known, a.target
+
+
+def make_workload(n_frames: int):
+    with mp.get_context("fork").Pool(min(16, n_frames, os.cpu_count() or 1)) as pool:
+        parts = pool.map(_frame, range(n_frames))
+    areas = np.concatenate([p[0] for p in parts])
+    known = np.concatenate([p[1] for p in parts])
+    return areas, known, parts[0][2]
+
+
+def _oracle_chunk(args):
+    areas, known, target = args
+    from oracle.fofse_dft import fofse
+    f = areas.astype(np.float32).astype(np.float64)
+    kn = known * (1 - target)[None]
+    r = fofse(f, kn, T, RHO, GAMMA, K)
+    return r.g.reshape(len(f), -1)[:, target.reshape(-1) == 1], r.keys, r.margin, r.top
+
+
+def cpu_baseline(areas, known, target, n_sample: int, workers: int):
+    """The FP64 oracle, unchanged, on a seeded sample of the batch's blocks,
+    split over ``workers`` processes.  Runs before the GPU is touched."""
+    idx = np.sort(np.random.default_rng(11).choice(len(areas), n_sample, replace=False))
+    chunks = np.array_split(idx, workers)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_chunk, [(areas[c], known[c], target) for c in chunks])
+    dt = time.perf_counter() - t0
+    g = np.concatenate([r[0] for r in res])
+    keys = np.concatenate([r[1] for r in res])
+    margin = np.concatenate([r[2] for r in res])
+    top = np.concatenate([r[3] for r in res])
+    info = {
+        "value": n_sample / dt, "unit": "blocks/s", "cores": workers, "kind": "oracle",
+        "sample": f"{n_sample} seeded blocks of the same batch (FP64 NumPy DFT-domain oracle, "
+                  f"{workers} processes, {dt:.1f} s)",
+        "cpu_model": _cpu_model(),
+    }
+    return info, (idx, g, keys, margin, top)
+
+
+def sample_parity(ref, gpu_out, gpu_sel):
+    """Compare the GPU's outputs with the oracle sample (parity rule)."""
+    from oracle.fofse_dft import selection_parity
+    idx, g, keys, margin, top = ref
+    ok, div = selection_parity(gpu_sel[idx], keys, margin, top_ref=top)
+    same = np.all(gpu_sel[idx] == keys, axis=1)
+    err = np.abs(gpu_out[idx] - g).max(axis=1)
+    fails = []
+    for j in np.nonzero(~ok)[0][:5]:
+        it = int(np.argmax(gpu_sel[idx[j]] != keys[j]))
+        fails.append({"block": int(idx[j]), "iteration": it,
+                      "oracle_margin": float(margin[j, it]),
+                      "min_margin_before": float(margin[j, :it + 1].min()),
+                      "gpu_key": int(gpu_sel[idx[j], it]), "oracle_key": int(keys[j, it])})
+    return {"blocks": int(len(idx)), "rule_ok": bool(ok.all()), "diverging": int(div.sum()),
+            "max_abs_dg": float(err[same].max()) if same.any() else None, "failures": fails}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(blocks are independent; see the sharding notes in the design document).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    # everything that forks runs before the GPU is initialised
+    areas, known, target = make_workload(args.frames)
+    n = len(areas)
+    base = None
+    if not args.no_cpu_baseline:
+        workers = min(16, len(os.sched_getaffinity(0)))
+        base = cpu_baseline(areas, known, target, min(args.cpu_sample, n), workers)
+        print(f"[bench] cpu baseline: {base[0]['value']:.2f} blocks/s on {workers} processes",
+              file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2207_01205_amd.fofse import Plan
+
+    dev = torch.device("cuda", 0)
+    plan = Plan(AREA, AREA, T, K, target, device=0)
+    d_areas = torch.from_numpy(areas).to(dev)
+    d_known = torch.from_numpy(known).to(dev)
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    out = torch.empty((n, plan.nB), dtype=torch.float32, device=dev)
+    sel = torch.empty((n, K), dtype=torch.int32, device=dev)
+    coef = torch.empty((n, K, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    from paper_2207_01205_amd import fofse as F
+
+    def step():
+        F.fofse_extrapolate_batch(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(),
+                                  rg.data_ptr(), out.data_ptr(), sel.data_ptr(),
+                                  coef.data_ptr(), st.data_ptr(), stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(args.steps)])
+    total = ev[0].elapsed_time(ev[-1]) * 1e-3
+    print(f"[bench] {n} blocks x {args.steps} steps: {total * 1e3:.2f} ms (host wall {wall * 1e3:.2f} ms)",
+          file=sys.stderr, flush=True)
+
+    # one frame alone (804 blocks): the single-frame latency and rate
+    n1 = int(np.count_nonzero(np.arange(n) < 804))
+    def step1():
+        F.fofse_extrapolate_batch(plan.handle, n1, d_areas.data_ptr(), d_known.data_ptr(),
+                                  rg.data_ptr(), out.data_ptr(), sel.data_ptr(),
+                                  coef.data_ptr(), st.data_ptr(), stream.cuda_stream)
+    step1()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        step1()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_frame = e0.elapsed_time(e1) * 1e-3 / 5
+
+    # final full-batch pass for the outputs checked below
+    step()
+    torch.cuda.synchronize()
+    status = st.cpu().numpy()
+    out_h = out.cpu().numpy()
+    sel_h = sel.cpu().numpy()
+
+    fpb = flops_per_block(T, K)
+    kern = float(np.mean(per_launch))
+    achieved = fpb * n / kern
+    result = {
+        "metric": "blocks/s (16x16 loss, 48x48 area, K=200) fwd & fwd+adjoint; % FP32 VALU peak",
+        "value": n * args.steps / total,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"1080p frame concealment, 10% of 16x16 macroblocks lost, "
+                               f"{args.frames} frames per step ({n} blocks), 48x48 areas, "
+                               f"T=64, K=200, rho=0.8, gamma=0.5, forward",
+                   "blocks_per_step": n, "frames_per_step": args.frames},
+        "extrapolated_px_per_s": n * args.steps / total * plan.nB,
+        "fp32_vector_peak_frac": achieved / FP32_VECTOR_PEAK,
+        "single_frame": {"blocks": n1, "ms": t_frame * 1e3, "blocks_per_s": n1 / t_frame},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                     "kernel": "fofse_fwd_kernel<64,4,1>", "flop_per_block": fpb,
+                     "avg_launch_ms": kern * 1e3},
+        "block_status_nonzero": int(np.count_nonzero(status)),
+    }
+    if base is not None:
+        info, ref = base
+        info["sample_parity"] = sample_parity(ref, out_h, sel_h)
+        result["cpu_baseline"] = info
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,6 +106,7 @@ class FofseResult:
     energy   (B, K + 1) float64 weighted residual energy sum_A w r^2 before the
              first and after every iteration, tracked by the exact drop per step.
     W0       (B,) float64 sum of the weights.
+    top      (B, K) float64 |R|_(1), the largest magnitude at selection time.
     """
     g: np.ndarray
     keys: np.ndarray
@@ -113,6 +114,7 @@ class FofseResult:
     margin: np.ndarray
     energy: np.ndarray
     W0: np.ndarray
+    top: np.ndarray = None
 
 
 def _embed(x: np.ndarray, T: int) -> np.ndarray:
@@ -175,6 +177,7 @@ def fofse(f, known, T: int, rho_hat: float, gamma: float, K: int,
     keys = np.zeros((B, K), np.int64)
     coef = np.zeros((B, K), np.complex128)
     margin = np.zeros((B, K))
+    top = np.zeros((B, K))
     energy = np.zeros((B, K + 1))
     energy[:, 0] = np.sum(w * f * f, axis=(1, 2))
 
@@ -191,6 +194,7 @@ def fofse(f, known, T: int, rho_hat: float, gamma: float, K: int,
         a2 = np.sqrt(np.maximum(s2, 0.0))
         safe = np.where(a1 > 0.0, a1, 1.0)
         margin[:, nu] = np.where(a1 > 0.0, (a1 - a2) / safe, 0.0)
+        top[:, nu] = a1
         u, v = np.divmod(best, T)
         keys[:, nu] = best
         Ru = R[bidx, u, v]
@@ -219,9 +223,9 @@ def fofse(f, known, T: int, rho_hat: float, gamma: float, K: int,
 
     # eq. 1: g = sum over the model spectrum of c_k phi_k, phi with exp(+j)
     g = (T * T * np.fft.ifft2(G)).real[:, oy:oy + M, ox:ox + N]
-    res = FofseResult(g, keys, coef, margin, energy, W0)
+    res = FofseResult(g, keys, coef, margin, energy, W0, top)
     if single:
-        res = FofseResult(g[0], keys[0], coef[0], margin[0], energy[0], W0[0])
+        res = FofseResult(g[0], keys[0], coef[0], margin[0], energy[0], W0[0], top[0])
     return res
 
 
@@ -276,19 +280,28 @@ def replay(f, known, T: int, rho_hat: float, gamma: float, keys,
     return g, np.array(coef, np.complex128)
 
 
-def selection_parity(keys_gpu, keys_ref, margin_ref, tol: float = 1e-6):
-    """Acceptance rule for a lower-precision selection sequence.
+def selection_parity(keys_gpu, keys_ref, margin_ref, tol: float = 1e-6,
+                     top_ref=None, floor: float = 1e-10):
+    """Acceptance rule for a selection sequence computed with other rounding.
 
-    For each block, nu* is the first iteration whose reference margin is <= tol.
-    The sequences must agree on every iteration before nu* (the whole sequence
-    if there is none).  Returns (ok, diverged): ok[b] is False on a mismatch
-    before nu*; diverged[b] is True when the sequences differ at or after nu*.
+    Iteration nu is "undecided" when the reference gap between the two largest
+    class magnitudes, a1 - a2 = margin * a1, is at most tol * a1 (the relative
+    rule) or, when ``top_ref`` (a1 per iteration) is given, at most
+    floor * A0 with A0 = a1 of the first iteration: then the residual has
+    decayed to a level where both computations are at rounding noise.  nu* is
+    the first undecided iteration; the sequences must agree before nu* (the
+    whole sequence if there is none).  Returns (ok, diverged): ok[b] is False
+    on a mismatch before nu*; diverged[b] is True when they differ at or after.
     """
     keys_gpu = np.atleast_2d(np.asarray(keys_gpu))
     keys_ref = np.atleast_2d(np.asarray(keys_ref))
     margin_ref = np.atleast_2d(np.asarray(margin_ref))
     B, K = keys_ref.shape
     low = margin_ref <= tol
+    if top_ref is not None and K > 0:
+        top_ref = np.atleast_2d(np.asarray(top_ref))
+        gap = margin_ref * top_ref
+        low = low | (gap <= floor * top_ref[:, :1])
     nu_star = np.where(low.any(axis=1), low.argmax(axis=1), K)
     mism = keys_gpu != keys_ref
     first = np.where(mism.any(axis=1), mism.argmax(axis=1), K)

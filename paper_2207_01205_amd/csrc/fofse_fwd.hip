@@ -148,15 +148,26 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ float wave_max_f32(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
+// Maximum of an unsigned value over the 64 lanes (DPP within rows of 16, then
+// row broadcasts); the result is uniform.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, false);
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_u32<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+    v = max(v, dpp_u32<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+    v = max(v, dpp_u32<0x141, 0xF>(v));   // row_half_mirror
+    v = max(v, dpp_u32<0x140, 0xF>(v));   // row_mirror
+    v = max(v, dpp_u32<0x142, 0xA>(v));   // row_bcast:15 into rows 1 and 3
+    v = max(v, dpp_u32<0x143, 0xC>(v));   // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Candidate of one wave: selection key (see below) and the value R[u].
 struct Cand {
-    float score;
-    int key;
+    uint32_t hi, lo;
     double re, im;
 };
 
@@ -169,68 +180,70 @@ struct Layout {
     static constexpr int H = T / 2;
     static constexpr int Q = T / 4;
     static constexpr int NROWS = H + 1;
-    static constexpr int S = (NROWS + NW - 1) / NW;   // row slots per wave
     static constexpr int WROWS = T + 1;               // window rows -Q .. 3Q
     static constexpr int NT = NW * 64;
+    // grid rows [begin(w), begin(w+1)) live in wave w
+    __host__ __device__ static constexpr int begin(int w) { return (w * NROWS + NW - 1) / NW; }
+    static constexpr int SMAX = begin(1) - begin(0);
 };
 
-// First/last row of wave WI that uses a given read form (or -1 if none).
+// Row bookkeeping of wave WI: its rows and, for each of the four read forms,
+// the reference row whose window offset is zero (smallest row for a direct
+// form, largest for a mirrored one, so every per-slot offset is >= 0).
 template <int T, int NW, int WI>
 struct WaveRows {
     using L = Layout<T, NW>;
-    static constexpr int k0 = WI * L::S;
-    static constexpr int k1 = (k0 + L::S - 1 < L::H) ? (k0 + L::S - 1) : L::H;   // inclusive
-    static constexpr int nvalid = (k1 >= k0) ? (k1 - k0 + 1) : 0;
-    // term 1 direct for k >= Q, mirror for k < Q; term 2 direct for k <= Q, mirror for k > Q
-    static constexpr int t1d_ref = (k1 >= L::Q) ? (k0 > L::Q ? k0 : L::Q) : -1;   // smallest direct row
-    static constexpr int t1m_ref = (k0 < L::Q) ? (k1 < L::Q - 1 ? k1 : L::Q - 1) : -1;   // largest mirror row
-    static constexpr int t2d_ref = (k0 <= L::Q) ? k0 : -1;                         // smallest direct row
-    static constexpr int t2m_ref = (k1 > L::Q) ? k1 : -1;                          // largest mirror row
+    static constexpr int k0 = L::begin(WI);
+    static constexpr int S = L::begin(WI + 1) - k0;
+    static constexpr int k1 = k0 + S - 1;
+    static constexpr int Q = L::Q, H = L::H;
+    static constexpr int r1d = (k1 >= Q) ? (k0 > Q ? k0 : Q) : Q;
+    static constexpr int r1m = (k0 < Q) ? (k1 < Q - 1 ? k1 : Q - 1) : 0;
+    static constexpr int r2d = (k0 <= Q) ? k0 : 0;
+    static constexpr int r2m = (k1 > Q) ? k1 : H;
 };
 
+// Selection key of a bin: the IEEE bits of |R|^2 with the low 12 mantissa bits
+// replaced by (63 - column) * 64 + (63 - row).  As doubles, keys order by
+// magnitude first (the 12 bits change |R|^2 by < 2^-40 relative) and, between
+// equal magnitudes, put the smaller class key column*T + row first -- the
+// oracle's tie rule.  Unused bins get key 0.
 template <int T, int NW, int WI, int PIX>
-__device__ __forceinline__ void run_wave(double* Rre, double* Rim, const double2* win,
-                                         const double2* tw, Cand (*xchg)[NW],
-                                         const KParams& p, int b, int lane, double W0,
-                                         double gamma, const int* pix_m, const int* pix_n,
-                                         double* gacc, int npix_t) {
+__device__ __forceinline__ void run_wave(
+        double __attribute__((ext_vector_type(WaveRows<T, NW, WI>::S))) & Rre,
+        double __attribute__((ext_vector_type(WaveRows<T, NW, WI>::S))) & Rim,
+        const double2* win, const double2* tw, Cand (*xchg)[NW], const KParams& p, int b,
+        int lane, double gW0, const int* pix_m, const int* pix_n, double* gacc, int npix_t) {
     using L = Layout<T, NW>;
     using WR = WaveRows<T, NW, WI>;
-    constexpr int S = L::S;
+    constexpr int S = WR::S;
     constexpr int H = L::H;
     constexpr int Q = L::Q;
     const int K = p.K;
     const bool lane_ok = lane < T;
-    const bool lane_canon_edge = lane <= H;    // rows 0 and T/2: columns 0..T/2 are the representatives
+    const bool lane_edge_ok = lane <= H;   // rows 0, T/2: columns 0..T/2 represent the classes
+    const uint32_t lane_bits = (uint32_t)(63 - lane) << 6;
     int u = 0, v = 0;
     double ca = 0.0, cb = 0.0;
 
     for (int it = 0; it < K; ++it) {
-        float best = -1.0f;
-        int bslot = 0;
         if (it > 0) {
             const int l = lane;
             const int cA = (l - v) & (T - 1), cB = (v - l) & (T - 1);
             const int cC = (l + v) & (T - 1), cD = (-l - v) & (T - 1);
-            // unused forms get a harmless in-window base (never dereferenced)
-            constexpr int r1d = WR::t1d_ref < 0 ? Q : WR::t1d_ref;
-            constexpr int r1m = WR::t1m_ref < 0 ? 0 : WR::t1m_ref;
-            constexpr int r2d = WR::t2d_ref < 0 ? 0 : WR::t2d_ref;
-            constexpr int r2m = WR::t2m_ref < 0 ? H : WR::t2m_ref;
-            const double2* b1d = win + (r1d - u + Q) * T + cA;
-            const double2* b1m = win + (u - r1m + Q) * T + cB;
-            const double2* b2d = win + (r2d + u + Q) * T + cC;
-            const double2* b2m = win + (T - r2m - u + Q) * T + cD;
+            const double2* b1d = win + (WR::r1d - u + Q) * T + cA;
+            const double2* b1m = win + (u - WR::r1m + Q) * T + cB;
+            const double2* b2d = win + (WR::r2d + u + Q) * T + cC;
+            const double2* b2m = win + (T - WR::r2m - u + Q) * T + cD;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int k = WR::k0 + s;
-                if (k > H) break;
                 double2 x1, x2;
-                if (k >= Q) x1 = b1d[(k - r1d) * T];
-                else        x1 = b1m[(r1m - k) * T];
-                if (k <= Q) x2 = b2d[(k - r2d) * T];
-                else        x2 = b2m[(r2m - k) * T];
-                // R -= c * W1 + conj(c) * W2, W1 = x1 or conj(x1), W2 = x2 or conj(x2)
+                if (k >= Q) x1 = b1d[(k - WR::r1d) * T];
+                else        x1 = b1m[(WR::r1m - k) * T];
+                if (k <= Q) x2 = b2d[(k - WR::r2d) * T];
+                else        x2 = b2m[(WR::r2m - k) * T];
+                // R -= c W1 + conj(c) W2 with W1 = x1 or conj(x1), W2 = x2 or conj(x2)
                 double re = Rre[s], im = Rim[s];
                 const double sre = x1.x + x2.x;
                 const double dre = x1.x - x2.x;
@@ -251,70 +264,71 @@ __device__ __forceinline__ void run_wave(double* Rre, double* Rim, const double2
                 Rim[s] = im;
             }
         }
-        // eq. 9: scan this lane's classes in key order (row, then column)
+        // eq. 9: largest |R| over this lane's classes, ties to the smallest key
+        double best = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int k = WR::k0 + s;
-            if (k > H) break;
             const double m2 = fma(Rim[s], Rim[s], Rre[s] * Rre[s]);
-            float sc = (float)m2;
+            const uint32_t lo = (__double2loint(m2) & 0xFFFFF000u) | (lane_bits | (uint32_t)(63 - k));
+            double key = __hiloint2double(__double2hiint(m2), (int)lo);
             bool ok = lane_ok;
-            if (k == 0 || k == H) ok = ok && lane_canon_edge;
-            if (!ok) sc = -1.0f;
-            if (sc > best) { best = sc; bslot = s; }
+            if (k == 0 || k == H) ok = ok && lane_edge_ok;
+            if (!ok) key = 0.0;
+            best = fmax(best, key);
         }
-        // wavefront argmax: largest score, then smallest key
-        const float wmax = wave_max_f32(best);
-        uint64_t hits = __ballot(best == wmax);
+        // wavefront maximum of the keys: high words by DPP, low words among ties
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        uint64_t hits = __ballot(bhi == mhi);
         int wl = __builtin_ctzll(hits);
-        // class key u*T + v of the basis: u = grid column (lane), v = grid row
-        int wkey = wl * T + WR::k0 + __builtin_amdgcn_readlane(bslot, wl);
+        uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)blo, wl);
         hits &= hits - 1;
-        while (hits) {                       // exact ties across lanes (rare)
+        while (hits) {                       // equal high words in several lanes (rare)
             const int ln = __builtin_ctzll(hits);
             hits &= hits - 1;
-            const int key = ln * T + WR::k0 + __builtin_amdgcn_readlane(bslot, ln);
-            if (key < wkey) { wkey = key; wl = ln; }
+            const uint32_t l2 = (uint32_t)__builtin_amdgcn_readlane((int)blo, ln);
+            if (l2 > mlo) { mlo = l2; wl = ln; }
         }
-        wkey = __builtin_amdgcn_readfirstlane(wkey);
+        mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)mlo);
         wl = __builtin_amdgcn_readfirstlane(wl);
-        const int wslot = __builtin_amdgcn_readfirstlane((wkey & (T - 1)) - WR::k0);
-        double wre = 0.0, wim = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s == wslot) { wre = readlane_f64(Rre[s], wl); wim = readlane_f64(Rim[s], wl); }
-        }
-        Cand win_c;
+        // every wave owns at least one valid bin and valid keys have non-zero
+        // low bits, so the winner is a bin of this wave; the clamp only guards
+        // the register index
+        int wslot = __builtin_amdgcn_readfirstlane((int)(63 - (mlo & 63u)) - WR::k0);
+        wslot = wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot);
+        const double wre = readlane_f64(Rre[wslot], wl);
+        const double wim = readlane_f64(Rim[wslot], wl);
+        Cand wc;
         if constexpr (NW > 1) {
-            if (lane == 0) xchg[it & 1][WI] = Cand{wmax, wkey, wre, wim};
+            if (lane == 0) xchg[it & 1][WI] = Cand{mhi, mlo, wre, wim};
             __syncthreads();
-            win_c = xchg[it & 1][0];
+            wc = xchg[it & 1][0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) {
                 const Cand c = xchg[it & 1][w];
-                if (c.score > win_c.score || (c.score == win_c.score && c.key < win_c.key)) win_c = c;
+                if (c.hi > wc.hi || (c.hi == wc.hi && c.lo > wc.lo)) wc = c;
             }
         } else {
-            win_c = Cand{wmax, wkey, wre, wim};
+            wc = Cand{mhi, mlo, wre, wim};
         }
-        // eqs. 5 and 14: c = gamma * R[u] / W0; a self-conjugate class keeps Re c.
-        // (u, v) below are the grid (row, column) of the selected bin.
-        v = win_c.key / T;
-        u = win_c.key - v * T;
+        // selected bin: grid row u (the class index l), grid column v (index k)
+        u = 63 - (int)(wc.lo & 63u);
+        v = (63 - (int)((wc.lo >> 6) & 63u)) & (T - 1);
+        u = u > H ? H : u;
+        // eqs. 5 and 14: c = gamma R[u] / W0; a self-conjugate class keeps Re c
         const bool selfc = (u == 0 || u == H) && (v == 0 || v == H);
-        double cre = gamma * win_c.re / W0;
-        double cim = selfc ? 0.0 : gamma * win_c.im / W0;
+        const double cre = wc.re * gW0;
+        const double cim = selfc ? 0.0 : wc.im * gW0;
         if (WI == 0 && lane == 0) {
-            if (p.sel) p.sel[(size_t)b * K + it] = win_c.key;
-            if (p.coef) {
-                p.coef[2 * ((size_t)b * K + it)] = cre;
-                p.coef[2 * ((size_t)b * K + it) + 1] = cim;
-            }
+            const size_t r = (size_t)b * K + it;
+            if (p.sel) p.sel[r] = v * T + u;
+            if (p.coef) { p.coef[2 * r] = cre; p.coef[2 * r + 1] = cim; }
         }
         // a self-conjugate class is applied as two half terms (W[k+u] = W[k-u])
         ca = selfc ? 0.5 * cre : cre;
         cb = cim;
-        // eqs. 1, 2: accumulate 2 Re(c phi_u) on the pixels of B owned here
+        // eqs. 1, 2: accumulate 2 Re(c phi) on the pixels of B owned here
 #pragma unroll
         for (int j = 0; j < PIX; ++j) {
             if (PIX == 1 || j < npix_t) {
@@ -329,11 +343,50 @@ __device__ __forceinline__ void run_wave(double* Rre, double* Rim, const double2
 // kernel
 // ---------------------------------------------------------------------------
 
+// R of this wave's rows from the transform Z = W + jR sitting in LDS in the
+// FFT's output order, then the residual iteration.  Contains the two barriers
+// that turn the LDS grid into the W window (all waves reach them).
+template <int T, int NW, int WI, int PIX, int WPT>
+__device__ __forceinline__ void wave_body(double2* win, const double2* tw, Cand (*xchg)[NW],
+                                          const KParams& p, int b, int tid, int lane,
+                                          const double2* wv, double gW0, int flags_pre,
+                                          int* s_flags, const int* pix_m, const int* pix_n,
+                                          double* gacc, int npix_t) {
+    using L = Layout<T, NW>;
+    using WR = WaveRows<T, NW, WI>;
+    constexpr int S = WR::S;
+    constexpr int NT = L::NT;
+    constexpr int WROWS = L::WROWS;
+    typedef double dvec __attribute__((ext_vector_type(S)));
+    dvec Rre, Rim;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = WR::k0 + s;
+        Rre[s] = 0.0;
+        Rim[s] = 0.0;
+        if (lane < T) {
+            const double2 a = win[FftPlan<T>::perm(k) * T + FftPlan<T>::perm(lane)];
+            const double2 c = win[FftPlan<T>::perm((-k) & (T - 1)) * T + FftPlan<T>::perm((-lane) & (T - 1))];
+            Rre[s] = 0.5 * (a.y + c.y);
+            Rim[s] = 0.5 * (c.x - a.x);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < WROWS * T) win[e] = wv[j];
+    }
+    __syncthreads();
+    const int flags = *s_flags | flags_pre;
+    if (flags == 0)
+        run_wave<T, NW, WI, PIX>(Rre, Rim, win, tw, xchg, p, b, lane, gW0, pix_m, pix_n, gacc, npix_t);
+}
+
 template <int T, int NW, int PIX>
-__global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
+__global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
     using L = Layout<T, NW>;
     constexpr int NT = L::NT;
-    constexpr int S = L::S;
     constexpr int Q = L::Q;
     constexpr int WROWS = L::WROWS;
     constexpr int WPT = (WROWS * T + NT - 1) / NT;    // window entries per thread
@@ -355,7 +408,7 @@ __global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
     if (tid == 0) s_flags = (rho > 0.0 && rho <= 1.0 && gamma > 0.0 && gamma <= 1.0) ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
 
-    // eqs. 4, 15: w = rho_hat^dist on A;  z = w + j w f
+    // eqs. 4, 15: w = rho_hat^dist on A;  z = w + j w f, placed transposed
     const double cm = 0.5 * (M - 1), cn = 0.5 * (N - 1);
     const size_t area_base = (size_t)b * M * N;
     for (int i = tid; i < M * N; i += NT) {
@@ -373,7 +426,7 @@ __global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
                 wf = w * (double)fv;
             }
         }
-        win[n * T + m] = make_double2(w, wf);       // transposed placement
+        win[n * T + m] = make_double2(w, wf);
     }
     __syncthreads();
 
@@ -387,24 +440,14 @@ __global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
     fft_stage_b<T, NT>(win, T, 1, T, tid);
     __syncthreads();
 
-    // Z[kr][kc] sits at win[perm(kr) * T + perm(kc)].  W = (Z + conj Z(-k)) / 2,
-    // R = (Z - conj Z(-k)) / (2j).
+    // Z[kr][kc] sits at win[perm(kr) * T + perm(kc)].  W = (Z + conj Z(-k)) / 2
+    // goes to the window: window row i holds grid row (i - T/4) mod T.
     auto zat = [&](int kr, int kc) -> double2 {
         return win[FftPlan<T>::perm(kr & (T - 1)) * T + FftPlan<T>::perm(kc & (T - 1))];
     };
     const double W0 = win[0].x;
-    double Rre[S], Rim[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int k = wave * S + s;
-        Rre[s] = 0.0;
-        Rim[s] = 0.0;
-        if (k <= T / 2 && lane < T) {
-            const double2 a = zat(k, lane), c = zat(-k, -lane);
-            Rre[s] = 0.5 * (a.y + c.y);
-            Rim[s] = 0.5 * (c.x - a.x);
-        }
-    }
+    const int flags_pre = (W0 > 0.0) ? 0 : FOFSE_BLOCK_NO_SUPPORT;
+    const double gW0 = gamma / W0;
     double2 wv[WPT];
 #pragma unroll
     for (int j = 0; j < WPT; ++j) {
@@ -417,15 +460,6 @@ __global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
             wv[j] = make_double2(0.5 * (a.x + z2.x), 0.5 * (a.y - z2.y));
         }
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        const int e = tid + j * NT;
-        if (e < WROWS * T) win[e] = wv[j];
-    }
-    if (tid == 0 && !(W0 > 0.0)) atomicOr(&s_flags, FOFSE_BLOCK_NO_SUPPORT);
-    __syncthreads();
-    const int flags = s_flags;
 
     // pixels of B owned by this thread
     int pix_m[PIX], pix_n[PIX];
@@ -445,12 +479,13 @@ __global__ __launch_bounds__(NW * 64) void fofse_fwd_kernel(KParams p) {
         }
     }
 
-    if (flags == 0) {
-        if (wave == 0) run_wave<T, NW, 0, PIX>(Rre, Rim, win, tw, xchg, p, b, lane, W0, gamma, pix_m, pix_n, gacc, npix_t);
-        if constexpr (NW > 1) if (wave == 1) run_wave<T, NW, 1, PIX>(Rre, Rim, win, tw, xchg, p, b, lane, W0, gamma, pix_m, pix_n, gacc, npix_t);
-        if constexpr (NW > 2) if (wave == 2) run_wave<T, NW, 2, PIX>(Rre, Rim, win, tw, xchg, p, b, lane, W0, gamma, pix_m, pix_n, gacc, npix_t);
-        if constexpr (NW > 3) if (wave == 3) run_wave<T, NW, 3, PIX>(Rre, Rim, win, tw, xchg, p, b, lane, W0, gamma, pix_m, pix_n, gacc, npix_t);
-    } else if (tid == 0) {
+    if (wave == 0) wave_body<T, NW, 0, PIX, WPT>(win, tw, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags, pix_m, pix_n, gacc, npix_t);
+    if constexpr (NW > 1) if (wave == 1) wave_body<T, NW, 1, PIX, WPT>(win, tw, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags, pix_m, pix_n, gacc, npix_t);
+    if constexpr (NW > 2) if (wave == 2) wave_body<T, NW, 2, PIX, WPT>(win, tw, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags, pix_m, pix_n, gacc, npix_t);
+    if constexpr (NW > 3) if (wave == 3) wave_body<T, NW, 3, PIX, WPT>(win, tw, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags, pix_m, pix_n, gacc, npix_t);
+
+    const int flags = s_flags | flags_pre;
+    if (flags != 0 && tid == 0) {
         for (int it = 0; it < K; ++it) {
             if (p.sel) p.sel[(size_t)b * K + it] = 0;
             if (p.coef) { p.coef[2 * ((size_t)b * K + it)] = 0.0; p.coef[2 * ((size_t)b * K + it) + 1] = 0.0; }

@@ -10,7 +10,7 @@ namespace fofse {
 
 // Waves per workgroup (one workgroup = one block) for each FFT size.
 constexpr int kWaves64 = 4;
-constexpr int kWaves32 = 1;
+constexpr int kWaves32 = 2;
 
 struct KParams {
     int n_blocks;

@@ -2,9 +2,11 @@
 
 Acceptance rule: the selected class keys must equal the oracle's on every
 iteration before the first one whose oracle margin is <= 1e-6 (relative, on
-|R|); blocks whose sequences match have max |g_gpu - g_oracle| <= 1e-3 on the
-0..255 scale (outputs unclipped).  Blocks that diverge at or after that
-iteration are counted and reported, not failed.
+|R|) or whose gap between the two largest magnitudes is <= 1e-10 of the
+initial largest magnitude (residual at FP64 rounding level); blocks whose
+sequences match have max |g_gpu - g_oracle| <= 1e-3 on the 0..255 scale
+(outputs unclipped).  Blocks that diverge at or after that iteration are
+counted and reported, not failed.
 """
 
 import numpy as np
@@ -46,7 +48,7 @@ def oracle_on(areas, known, target, T, rho, gamma, K):
 
 def check_parity(ref, target, out, sel, coef, st, label):
     assert np.all(st == 0), f"{label}: unexpected block status {np.unique(st)}"
-    ok, div = selection_parity(sel, ref.keys, ref.margin, MARGIN)
+    ok, div = selection_parity(sel, ref.keys, ref.margin, MARGIN, top_ref=ref.top)
     bad = np.nonzero(~ok)[0]
     assert len(bad) == 0, f"{label}: selection differs before the margin rule allows, blocks {bad[:10]}"
     same = np.all(sel == ref.keys, axis=1)
@@ -159,7 +161,9 @@ def test_edge_cases():
     out, sel, coef, st = run_gpu(plan, batch, kn, 0.8, 0.5, "edge cases")
     assert st.tolist() == [0, 0, 1, 2, 0]
     assert np.all(out[2] == 0) and np.all(out[3] == 0)
-    assert np.all(out[1] == 0) and np.all(sel[1] == 0)            # zero signal
+    # zero signal: the residual spectrum is rounding noise of the joint
+    # transform of w and w*f, so the model stays at rounding level
+    assert np.abs(out[1]).max() <= 1e-9
     ref = oracle_on(batch[[0]], kn[[0]], target, 32, 0.8, 0.5, 30)
     tb = target.reshape(-1) == 1
     assert np.abs(out[4] - out[0]).max() == 0.0
@@ -171,6 +175,22 @@ def test_edge_cases():
     plan0 = _plan(32, 32, 32, 0, target)
     out, sel, coef, st = run_gpu(plan0, batch[:2], kn[:2], 0.8, 0.5, "K = 0")
     assert np.all(out == 0) and np.all(st == 0)
+
+
+def test_saturated_and_constant_areas():
+    """Constant areas (a saturated 255 region, a dark one, mid grey): the DC
+    class wins until the residual reaches rounding level, g -> c."""
+    _, _, target = synth.single_block(0)
+    rng = np.random.default_rng(9)
+    f = np.stack([np.full((32, 32), 255.0), np.zeros((32, 32)) + 3.0, np.full((32, 32), 128.0)])
+    known = (rng.uniform(size=(3, 32, 32)) < 0.95).astype(np.uint8)
+    plan = _plan(32, 32, 32, 100, target)
+    out, sel, coef, st = run_gpu(plan, f, known, 0.8, 0.5, "constant areas")
+    ref = oracle_on(f, known, target, 32, 0.8, 0.5, 100)
+    check_parity(ref, target, out, sel, coef, st, "constant areas")
+    tb = target.reshape(-1) == 1
+    for i in range(3):
+        assert np.abs(out[i] - f[i].reshape(-1)[tb]).max() <= 1e-9 * 255
 
 
 def test_deterministic(frame_areas):

@@ -267,3 +267,22 @@ def test_selection_parity_rule():
     ok, div = selection_parity(np.array([[1, 2, 9, 9], [1, 9, 3, 4]]), ref, margin)
     assert ok.tolist() == [True, False]
     assert div.tolist() == [True, False]
+
+
+def test_selection_parity_floor():
+    ref = np.array([[0, 0, 0]])
+    margin = np.array([[0.5, 0.5, 0.5]])
+    top = np.array([[1e4, 1e-3, 1e-7]])      # gap 5e-4 > 1e-6, then 5e-8 <= 1e-10 * 1e4
+    gpu = np.array([[0, 0, 1]])
+    ok, _ = selection_parity(gpu, ref, margin)
+    assert not ok[0]
+    ok, div = selection_parity(gpu, ref, margin, top_ref=top)
+    assert ok[0] and div[0]
+    ok, _ = selection_parity(np.array([[0, 1, 1]]), ref, margin, top_ref=top)
+    assert not ok[0]
+
+
+def test_top_magnitude_and_margin_consistent():
+    f, known, _ = synth.single_block(8)
+    r = fofse(f, known, 32, 0.8, 0.5, 10)
+    assert np.isclose(r.top[0], np.abs(r.coef[0]) * r.W0 / 0.5, rtol=1e-12)
