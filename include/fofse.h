@@ -37,7 +37,7 @@ typedef enum {
     FOFSE_OK = 0,
     FOFSE_ERR_ARG = 1,          /* invalid argument (NULL, size, range)       */
     FOFSE_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. an FFT size)     */
-    FOFSE_ERR_NOMEM = 3,        /* device allocation failed (create only)     */
+    FOFSE_ERR_NOMEM = 3,        /* device allocation failed                   */
     FOFSE_ERR_DEVICE = 4        /* a HIP call or a kernel launch failed       */
 } fofse_status;
 
@@ -79,6 +79,24 @@ fofse_status fofse_create(const fofse_geometry* geometry, int32_t device,
 int32_t fofse_target_count(fofse_plan plan);
 
 /*
+ * Kernel organisation used by fofse_extrapolate_batch (results are the same
+ * up to rounding of the shared transform; each path is deterministic):
+ *   FOFSE_PATH_AUTO    (default) grouped when supported and the batch holds at
+ *                      least 8 blocks per compute unit, split otherwise;
+ *   FOFSE_PATH_SPLIT   one workgroup per block, the block's rows spread over
+ *                      several wavefronts (lowest latency for few blocks);
+ *   FOFSE_PATH_GROUPED blocks with identical support masks grouped on the device;
+ *                      one wavefront per block, one shared W per workgroup
+ *                      (highest throughput).  Needs fft_size 64.
+ * Returns FOFSE_ERR_ARG for a NULL plan or unknown path, FOFSE_ERR_UNSUPPORTED
+ * if the grouped path cannot run this geometry.
+ */
+#define FOFSE_PATH_AUTO    0
+#define FOFSE_PATH_SPLIT   1
+#define FOFSE_PATH_GROUPED 2
+fofse_status fofse_set_path(fofse_plan plan, int32_t path);
+
+/*
  * Extrapolate n_blocks areas of the plan's geometry (Sections 2 and 3).
  *
  * For every block b, K iterations of FOFSE run in the DFT domain: the weighted
@@ -108,15 +126,38 @@ int32_t fofse_target_count(fofse_plan plan);
  *   d_status     device int32 [n_blocks] or NULL: FOFSE_BLOCK_* bits.
  *   stream       hipStream_t (as void*), NULL for the null stream.
  *
+ * The model on B is synthesised from the selection record, so when d_sel or
+ * d_coef is NULL the plan keeps a record of its own (12 B per block and
+ * iteration, grown when a larger batch arrives).
+ *
  * Returns FOFSE_ERR_ARG (NULL plan or required pointer, n_blocks < 0),
- * FOFSE_ERR_DEVICE if the launch fails, FOFSE_OK otherwise.  n_blocks == 0 is
- * a no-op.
+ * FOFSE_ERR_NOMEM if a plan-owned buffer (the record above, or the grouped
+ * path's workspace of about 20 B per hash slot + 32 B per block) cannot be
+ * allocated, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
+ * n_blocks == 0 is a no-op.
  */
 fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
                                      const float* d_areas, const uint8_t* d_known,
                                      const double* d_rho_gamma, float* d_out,
                                      int32_t* d_sel, double* d_coef,
                                      int32_t* d_status, void* stream);
+
+/*
+ * Profiling hook.  With timing enabled, every fofse_extrapolate_batch call
+ * records a pair of HIP events on its stream around its main kernel (the
+ * iteration kernel; the weight, grouping and synthesis kernels are outside).
+ * The plan keeps the pairs of the last 256 calls.
+ *   fofse_set_timing    enable (non-zero) or disable; enabling clears the ring.
+ *                       FOFSE_ERR_ARG for a NULL plan, FOFSE_ERR_DEVICE if the
+ *                       events cannot be created.
+ *   fofse_kernel_times  waits for those events and writes the main-kernel
+ *                       durations in milliseconds of up to `max` most recent
+ *                       calls (oldest first) to host ms_out; returns how many
+ *                       were written (0 for a NULL plan or ms_out, or when
+ *                       timing is off).
+ */
+fofse_status fofse_set_timing(fofse_plan plan, int32_t enable);
+int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
 
 /* Release the plan and its device memory.  NULL is ignored. */
 void fofse_destroy(fofse_plan plan);

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfofse.so")
-SOURCES = ["fofse_fwd.hip", "fofse_api.cpp"]
+SOURCES = ["fofse_fwd.hip", "fofse_group.hip", "fofse_api.cpp"]
 ARCH = "gfx950"
 
 
@@ -31,6 +31,9 @@ def build(verbose: bool = False, extra=()) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            # no packed FP32 instructions anywhere in the device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # IEEE mode off: v_max_f64 needs no operand canonicalisation (the
+           # kernels carry no NaNs; input checks test exponent bits instead)
+           "-mno-amdgpu-ieee", "-fno-honor-nans",
            "-Wno-unused-command-line-argument",
            "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + list(extra)
     if verbose:

@@ -14,13 +14,33 @@
 
 struct fofse_plan_s {
     int device = 0;
+    int n_cu = 0;
+    int path = FOFSE_PATH_AUTO;
     int M = 0, N = 0, T = 0, K = 0, nB = 0;
     uint8_t* d_target = nullptr;
     int32_t* d_bpix = nullptr;
     double2* d_twiddle = nullptr;
+    double* d_wtab = nullptr;       // rho_hat ** dist per sample, refreshed per call
+    // grouped-path workspace, grown on demand (capacity in blocks)
+    int ws_blocks = 0;
+    int ws_hsize = 0;
+    void* d_ws = nullptr;
+    // profiling: event pairs around the main kernel of the last kRing calls
+    bool timing = false;
+    hipEvent_t ev_start[256] = {};
+    hipEvent_t ev_stop[256] = {};
+    long long n_timed = 0;
+    // selection record used when the caller passes no d_sel / d_coef
+    size_t rec_blocks = 0;
+    int32_t* d_rec_sel = nullptr;
+    double* d_rec_coef = nullptr;
 };
 
 namespace {
+
+// Below this many blocks per compute unit the split path (several waves per
+// block) finishes sooner than the grouped path (one wave per block).
+constexpr int kGroupedMinBlocksPerCu = 8;
 
 bool fft_size_built(int T) { return T == 32 || T == 64; }
 
@@ -37,12 +57,81 @@ struct DeviceGuard {
     }
 };
 
+constexpr int kRing = 256;
+
+void free_events(fofse_plan p) {
+    for (int i = 0; i < kRing; ++i) {
+        if (p->ev_start[i]) (void)hipEventDestroy(p->ev_start[i]);
+        if (p->ev_stop[i]) (void)hipEventDestroy(p->ev_stop[i]);
+        p->ev_start[i] = p->ev_stop[i] = nullptr;
+    }
+}
+
 void free_plan(fofse_plan p) {
     if (!p) return;
+    free_events(p);
+    if (p->d_ws) (void)hipFree(p->d_ws);
+    if (p->d_rec_sel) (void)hipFree(p->d_rec_sel);
+    if (p->d_rec_coef) (void)hipFree(p->d_rec_coef);
     if (p->d_target) (void)hipFree(p->d_target);
     if (p->d_bpix) (void)hipFree(p->d_bpix);
     if (p->d_twiddle) (void)hipFree(p->d_twiddle);
+    if (p->d_wtab) (void)hipFree(p->d_wtab);
     delete p;
+}
+
+bool grouped_supported(const fofse_plan_s* p) {
+    return p->T == 64 && p->nB <= fofse::group_max_target_samples() && p->M * p->N <= 64 * 64;
+}
+
+// Workspace of the grouped path for n blocks: hash table of hsize slots
+// (key 8 B, representative, count, first item: 4 B each), per-block class and
+// position, per-item block list, size and class, three counters.
+fofse_status ensure_workspace(fofse_plan p, int n, fofse::GroupArgs& g) {
+    int hsize = 64;
+    while (hsize < 2 * n) hsize <<= 1;
+    if (n > p->ws_blocks || hsize > p->ws_hsize) {
+        if (p->d_ws) (void)hipFree(p->d_ws);
+        p->d_ws = nullptr;
+        p->ws_blocks = p->ws_hsize = 0;
+        const size_t bytes = (size_t)hsize * 20 + (size_t)n * (8 + 4 * fofse::kGroup + 8) + 64;
+        if (hipMalloc(&p->d_ws, bytes) != hipSuccess) return FOFSE_ERR_NOMEM;
+        p->ws_blocks = n;
+        p->ws_hsize = hsize;
+    }
+    hsize = p->ws_hsize;
+    const int cap = p->ws_blocks;
+    char* c = (char*)p->d_ws;
+    g.hsize = hsize;
+    g.hmask = (uint32_t)(hsize - 1);
+    g.ht_key = (unsigned long long*)c; c += (size_t)hsize * 8;
+    g.ht_rep = (int*)c; c += (size_t)hsize * 4;
+    g.ht_cnt = (int*)c; c += (size_t)hsize * 4;
+    g.item_start = (int*)c; c += (size_t)hsize * 4;
+    g.cls = (int*)c; c += (size_t)cap * 4;
+    g.pos = (int*)c; c += (size_t)cap * 4;
+    g.item_blk = (int*)c; c += (size_t)cap * 4 * fofse::kGroup;
+    g.item_n = (int*)c; c += (size_t)cap * 4;
+    g.item_cls = (int*)c; c += (size_t)cap * 4;
+    g.n_single = (int*)c; c += 16;
+    g.counts = (int*)c;
+    return FOFSE_OK;
+}
+
+// Record of n blocks (K keys, K coefficients each) owned by the plan.
+fofse_status ensure_record(fofse_plan p, int n) {
+    if ((size_t)n <= p->rec_blocks) return FOFSE_OK;
+    if (p->d_rec_sel) (void)hipFree(p->d_rec_sel);
+    if (p->d_rec_coef) (void)hipFree(p->d_rec_coef);
+    p->d_rec_sel = nullptr;
+    p->d_rec_coef = nullptr;
+    p->rec_blocks = 0;
+    const size_t k = p->K > 0 ? (size_t)p->K : 1;
+    if (hipMalloc(&p->d_rec_sel, (size_t)n * k * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&p->d_rec_coef, (size_t)n * k * 2 * sizeof(double)) != hipSuccess)
+        return FOFSE_ERR_NOMEM;
+    p->rec_blocks = (size_t)n;
+    return FOFSE_OK;
 }
 
 }  // namespace
@@ -86,14 +175,19 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
 
     DeviceGuard guard(device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return FOFSE_ERR_DEVICE;
     fofse_plan p = new (std::nothrow) fofse_plan_s;
     if (!p) return FOFSE_ERR_NOMEM;
     p->device = device;
+    p->n_cu = n_cu;
     p->M = M; p->N = N; p->T = T; p->K = K;
     p->nB = (int)bpix.size();
     if (hipMalloc(&p->d_target, M * N) != hipSuccess ||
         hipMalloc(&p->d_bpix, bpix.size() * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&p->d_twiddle, T * sizeof(double2)) != hipSuccess) {
+        hipMalloc(&p->d_twiddle, T * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->d_wtab, (size_t)M * N * sizeof(double)) != hipSuccess) {
         free_plan(p);
         return FOFSE_ERR_NOMEM;
     }
@@ -108,6 +202,48 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
 }
 
 int32_t fofse_target_count(fofse_plan p) { return p ? p->nB : 0; }
+
+fofse_status fofse_set_path(fofse_plan p, int32_t path) {
+    if (!p || path < FOFSE_PATH_AUTO || path > FOFSE_PATH_GROUPED) return FOFSE_ERR_ARG;
+    if (path == FOFSE_PATH_GROUPED && !grouped_supported(p)) return FOFSE_ERR_UNSUPPORTED;
+    p->path = path;
+    return FOFSE_OK;
+}
+
+fofse_status fofse_set_timing(fofse_plan p, int32_t enable) {
+    if (!p) return FOFSE_ERR_ARG;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return FOFSE_ERR_DEVICE;
+    if (enable) {
+        for (int i = 0; i < kRing; ++i) {
+            if (!p->ev_start[i] && hipEventCreate(&p->ev_start[i]) != hipSuccess) return FOFSE_ERR_DEVICE;
+            if (!p->ev_stop[i] && hipEventCreate(&p->ev_stop[i]) != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        p->n_timed = 0;
+        p->timing = true;
+    } else {
+        p->timing = false;
+    }
+    return FOFSE_OK;
+}
+
+int32_t fofse_kernel_times(fofse_plan p, float* ms_out, int32_t max) {
+    if (!p || !ms_out || max <= 0 || !p->timing) return 0;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return 0;
+    long long n = p->n_timed < kRing ? p->n_timed : kRing;
+    if (n > max) n = max;
+    int32_t w = 0;
+    for (long long c = p->n_timed - n; c < p->n_timed; ++c) {
+        const int i = (int)(c % kRing);
+        float ms = 0.0f;
+        if (hipEventSynchronize(p->ev_stop[i]) != hipSuccess ||
+            hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]) != hipSuccess)
+            return w;
+        ms_out[w++] = ms;
+    }
+    return w;
+}
 
 fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float* d_areas,
                                      const uint8_t* d_known, const double* d_rho_gamma,
@@ -127,11 +263,46 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
     k.bpix = p->d_bpix;
     k.rho_gamma = d_rho_gamma;
     k.twiddle = p->d_twiddle;
+    k.wtab = p->d_wtab;
     k.out = d_out;
     k.sel = d_sel;
     k.coef = d_coef;
     k.status = d_status;
-    hipError_t e = fofse::launch_forward(k, (hipStream_t)stream);
+    if (!d_sel || !d_coef) {
+        const fofse_status rs = ensure_record(p, n_blocks);
+        if (rs != FOFSE_OK) return rs;
+        if (!d_sel) k.sel = p->d_rec_sel;
+        if (!d_coef) k.coef = p->d_rec_coef;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    bool grouped = false;
+    if (p->path == FOFSE_PATH_GROUPED) grouped = true;
+    else if (p->path == FOFSE_PATH_AUTO)
+        grouped = grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu;
+    hipError_t e;
+    fofse::Timing tm{};
+    if (p->timing) {
+        const int i = (int)(p->n_timed % kRing);
+        tm.start = p->ev_start[i];
+        tm.stop = p->ev_stop[i];
+        ++p->n_timed;
+    }
+    if (grouped) {
+        fofse::GroupArgs g{};
+        g.MN = p->M * p->N;
+        g.known = d_known;
+        g.target = p->d_target;
+        g.direct = d_known == nullptr;
+        if (!g.direct) {
+            const fofse_status ws = ensure_workspace(p, n_blocks, g);
+            if (ws != FOFSE_OK) return ws;
+            e = fofse::launch_clear(g, st);
+            if (e != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        e = fofse::launch_grouped(k, g, p->n_cu, st, tm);
+    } else {
+        e = fofse::launch_forward(k, st, tm);
+    }
     return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
 }
 

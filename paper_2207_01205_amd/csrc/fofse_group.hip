@@ -1,0 +1,404 @@
+// Grouped FOFSE forward for gfx950: blocks whose support areas have the same
+// known-sample mask share one weighting function w, hence one W = DFT(w)
+// (eq. 4 / eq. 15 depend only on the mask).  A workgroup takes up to kGroup
+// such blocks, keeps ONE W window in LDS for all of them and gives each block a
+// whole wavefront: lane = grid column, register slot = grid row 0..T/2.  The
+// iteration (eqs. 3, 5, 9, 14 in the DFT domain; eqs. 1, 2 for the model) then
+// runs with no cross-wave exchange at all.
+//
+// Grouping runs on the device:
+//   k_mask_hash   64-bit hash of each block's mask, inserted into an open-address
+//                 table (the first inserter becomes the class representative)
+//   k_group_count exact byte comparison with the representative; position of
+//                 the block inside its class (blocks that differ from their
+//                 representative on a hash collision become singletons)
+//   k_group_scan  work items per class (ceil(count / kGroup)) -> item offsets
+//   k_group_fill  item -> list of its blocks
+// The main kernel is persistent: workgroup g processes a contiguous range of
+// items, so consecutive items of one class land on the same workgroup.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "fofse_kernel.h"
+#include "iterate.hpp"
+
+namespace fofse {
+
+// ---------------------------------------------------------------------------
+// grouping kernels (one wavefront per block unless stated)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // splitmix64 finaliser
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ bool eff_known(const uint8_t* known, const uint8_t* target, size_t base, int i) {
+    return target[i] == 0 && (known == nullptr || known[base + i] != 0);
+}
+
+__device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, off, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), off, 64);
+        v ^= ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_mask_hash(GroupArgs g) {
+    const int b = (int)__builtin_amdgcn_workgroup_id_x(), lane = (int)__builtin_amdgcn_workitem_id_x();
+    const size_t base = (size_t)b * g.MN;
+    uint64_t h = 0;
+    for (int i = lane; i < g.MN; i += 64)
+        if (eff_known(g.known, g.target, base, i)) h ^= mix64((uint64_t)i);
+    h = wave_xor_u64(h) | 1ull;          // 0 marks an empty table slot
+    if (lane == 0) {
+        uint32_t slot = (uint32_t)(h >> 17) & g.hmask;
+        for (;;) {
+            const unsigned long long prev = atomicCAS(&g.ht_key[slot], 0ull, (unsigned long long)h);
+            if (prev == 0ull) { g.ht_rep[slot] = b; break; }
+            if (prev == h) break;
+            slot = (slot + 1) & g.hmask;
+        }
+        g.cls[b] = (int)slot;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_group_count(GroupArgs g) {
+    const int b = (int)__builtin_amdgcn_workgroup_id_x(), lane = (int)__builtin_amdgcn_workitem_id_x();
+    const int slot = g.cls[b];
+    const int rep = g.ht_rep[slot];
+    const size_t base = (size_t)b * g.MN, rbase = (size_t)rep * g.MN;
+    bool same = true;
+    for (int i = lane; i < g.MN; i += 64)
+        same = same && (eff_known(g.known, g.target, base, i) == eff_known(g.known, g.target, rbase, i));
+    same = __all(same);
+    if (lane == 0) {
+        if (same) {
+            g.pos[b] = atomicAdd(&g.ht_cnt[slot], 1);
+        } else {
+            g.pos[b] = atomicAdd(g.n_single, 1);
+            g.cls[b] = -1;
+        }
+    }
+}
+
+// One workgroup of 1024 threads: items per slot and their exclusive prefix.
+__global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
+    __shared__ int part[1024];
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    const int per = (g.hsize + 1023) / 1024;
+    const int s0 = tid * per;
+    int sum = 0;
+    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + kGroup - 1) / kGroup;
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {       // inclusive scan (Hillis-Steele)
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;
+    for (int s = s0; s < s0 + per && s < g.hsize; ++s) {
+        g.item_start[s] = run;
+        run += (g.ht_cnt[s] + kGroup - 1) / kGroup;
+    }
+    if (tid == 1023) {
+        g.counts[0] = part[1023];                    // grouped items
+        g.counts[1] = part[1023] + *g.n_single;      // all items
+    }
+}
+
+__global__ void k_group_fill(GroupArgs g, int n) {
+    const int b = (int)__builtin_amdgcn_workgroup_id_x() * 256 + (int)__builtin_amdgcn_workitem_id_x();
+    if (b >= n) return;
+    const int slot = g.cls[b];
+    const int pos = g.pos[b];
+    int item, j, cnt;
+    if (slot >= 0) {
+        item = g.item_start[slot] + pos / kGroup;
+        j = pos % kGroup;
+        const int c = g.ht_cnt[slot] - (pos / kGroup) * kGroup;
+        cnt = c < kGroup ? c : kGroup;
+    } else {
+        item = g.counts[0] + pos;
+        j = 0;
+        cnt = 1;
+    }
+    g.item_blk[(size_t)item * kGroup + j] = b;
+    if (j == 0) {
+        g.item_n[item] = cnt;
+        g.item_cls[item] = slot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// last FFT stage of W written straight into the window layout
+// ---------------------------------------------------------------------------
+
+// The 64 stored columns of a 64-point transform split into two halves, each
+// closed under the output permutation perm(c) = 8 (c % 8) + c / 8 (which swaps
+// the octal digits of c): first 32 entries = half A, last 32 = half B.
+__constant__ int kColHalves[64] = {
+    0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 16, 17, 18, 19, 20, 24, 25, 26, 27,
+    32, 33, 34, 40, 41, 48, 49, 56,
+    15, 21, 22, 23, 28, 29, 30, 31, 35, 36, 37, 38, 39, 42, 43, 44, 45, 46, 47, 50, 51, 52,
+    53, 54, 55, 57, 58, 59, 60, 61, 62, 63};
+
+// Stage B of the column pass of a 64 x 64 FFT, written into the W window:
+// window row i (0..64) holds grid row (i - 16) mod 64, columns in natural order.
+// The outputs of stored column pc go to LDS column perm(pc), which lies in the
+// same half as pc.  Each half is read into registers, then written after a
+// barrier, so the in-place reshuffle never clobbers an unread input.
+template <int NT>
+__device__ __forceinline__ void fft64_stage_b_to_window(double2* win, int tid) {
+    constexpr int T = 64, Q = 16;
+    static_assert(NT == 256, "one stage-B task per thread and half");
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        // half A first, then half B: the writes of a half only touch columns of
+        // that half, whose inputs have all been read before the barrier
+        const int t = half * NT + tid;
+        const int pc = kColHalves[t >> 3];
+        const int k1 = t & 7;
+        double2 x[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) x[n2] = win[(8 * k1 + n2) * T + pc];
+        dft8(x);
+        __syncthreads();
+        const int c = FftPlan<T>::perm(pc);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            const int k = k1 + 8 * k2;                 // natural grid row
+            win[((k + Q) & (T - 1)) * T + c] = x[k2];
+            if (k == 3 * Q) win[T * T + c] = x[k2];    // window row 64 repeats grid row 48
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// persistent grouped kernel: kGroup blocks x kWavesG waves per workgroup
+// ---------------------------------------------------------------------------
+
+constexpr int kWavesG = 1;                  // waves per block in the grouped path
+
+template <int T, int WI>
+__device__ __forceinline__ void extract_rows(const double2* win, int lane,
+                                             RegSpec<WaveRows<T, kWavesG, WI>::S>& R) {
+    using WR = WaveRows<T, kWavesG, WI>;
+#pragma unroll
+    for (int s = 0; s < WR::S; ++s) {
+        const int k = WR::k0 + s;
+        double2 a = make_double2(0.0, 0.0);
+        if (lane < T) a = win[FftPlan<T>::perm(k) * T + FftPlan<T>::perm(lane)];
+        R.set(s, a.x, a.y);
+    }
+}
+
+// LDS of the grouped kernel.
+template <int T>
+struct GroupShared {
+    double2 win[(T + 1) * T];
+    double2 tw[T];
+    Xchg<kWavesG> xchg[kGroup][2];
+    int flags[kGroup];
+};
+
+// One work item (up to kGroup blocks of one mask class) as seen by wave WI of
+// its block.  Every wave of the workgroup runs the same sequence of barriers.
+template <int T, int WI, int MAXPX>
+__device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& p, const GroupArgs& g,
+                                             int item, int tid, int lane, int jblk, int tib,
+                                             bool params_ok, double rho, double gamma) {
+    constexpr int NT = kGroup * kWavesG * 64;
+    const int M = p.M, N = p.N, MN = M * N, K = p.K;
+    double2* win = sh.win;
+    int nblk, blk[kGroup];
+    if (g.direct) {
+        nblk = min(kGroup, p.n_blocks - item * kGroup);
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) blk[j] = item * kGroup + j;
+    } else {
+        nblk = g.item_n[item];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) blk[j] = g.item_blk[(size_t)item * kGroup + j];
+    }
+    const int b_rep = blk[0];              // every block of the item has this mask
+    __syncthreads();                       // previous item done with LDS
+    if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+
+    // weights of this thread's samples (eqs. 4, 15): identical for the item
+    double wreg[MAXPX];
+#pragma unroll
+    for (int q = 0; q < MAXPX; ++q) {
+        const int i = tid + q * NT;
+        wreg[q] = 0.0;
+        if (i < MN && eff_known(g.known, p.target, (size_t)b_rep * MN, i)) wreg[q] = p.wtab[i];
+    }
+
+    // R = DFT(w f) of each block by its own transform (eqs. 7, 8), so that a
+    // block's result does not depend on which blocks share its work item
+    RegSpec<WaveRows<T, kWavesG, WI>::S> R;
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+        if (j >= nblk) break;                  // uniform over the workgroup
+        __syncthreads();
+        for (int i = tid; i < T * T; i += NT) win[i] = make_double2(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q) {
+            const int i = tid + q * NT;
+            if (i < MN) {
+                const int m = i / N, n = i - m * N;
+                double fw = 0.0;
+                if (wreg[q] != 0.0) {
+                    const float x = p.areas[(size_t)blk[j] * MN + i];
+                    if ((__float_as_uint(x) & 0x7f800000u) == 0x7f800000u) atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
+                    else fw = wreg[q] * (double)x;
+                }
+                win[n * T + m] = make_double2(fw, 0.0);        // transposed placement
+            }
+        }
+        __syncthreads();
+        fft_stage_a<T, NT>(win, sh.tw, N, T, 1, tid);
+        __syncthreads();
+        fft_stage_b<T, NT>(win, N, T, 1, tid);
+        __syncthreads();
+        fft_stage_a<T, NT>(win, sh.tw, T, 1, T, tid);
+        __syncthreads();
+        fft_stage_b<T, NT>(win, T, 1, T, tid);
+        __syncthreads();
+        if (jblk == j) extract_rows<T, WI>(win, lane, R);
+    }
+
+    // W = DFT(w) straight into the window (rows -T/4 .. 3T/4)
+    __syncthreads();
+    for (int i = tid; i < T * T; i += NT) win[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXPX; ++q) {
+        const int i = tid + q * NT;
+        if (i < MN) {
+            const int m = i / N, n = i - m * N;
+            win[n * T + m] = make_double2(wreg[q], 0.0);
+        }
+    }
+    __syncthreads();
+    fft_stage_a<T, NT>(win, sh.tw, N, T, 1, tid);
+    __syncthreads();
+    fft_stage_b<T, NT>(win, N, T, 1, tid);
+    __syncthreads();
+    fft_stage_a<T, NT>(win, sh.tw, T, 1, T, tid);
+    __syncthreads();
+    fft64_stage_b_to_window<NT>(win, tid);
+    const double W0 = win[16 * T].x;      // W[0, 0] sits in window row 16
+
+    // the K iterations: every wave runs them (and their barriers); waves of a
+    // missing or flagged block compute on zeros and write nothing
+    const bool present = jblk < nblk;
+    int flags = present ? sh.flags[jblk] : 0;
+    if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
+    const bool live = present && flags == 0;
+    const int bj = blk[jblk];
+    const double gW0 = live ? gamma / W0 : 0.0;
+    if (kWavesG > 1 || live)
+        run_wave<T, kWavesG, WI>(R, win, sh.xchg[jblk], p, bj, lane, gW0, live);
+    if (present) {
+        if (!live) {          // empty record: the synthesised model is 0
+            for (int it = tib; it < K; it += kWavesG * 64) {
+                p.sel[(size_t)bj * K + it] = 0;
+                p.coef[2 * ((size_t)bj * K + it)] = 0.0;
+                p.coef[2 * ((size_t)bj * K + it) + 1] = 0.0;
+            }
+        }
+        if (p.status && tib == 0) p.status[bj] = flags;
+    }
+}
+
+template <int T, int MAXPX>
+__global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(KParams p, GroupArgs g) {
+    constexpr int NT = kGroup * kWavesG * 64;
+    static_assert(T == 64, "the window stage is written for T = 64");
+    __shared__ GroupShared<T> sh;
+
+    const int tid = (int)__builtin_amdgcn_workitem_id_x(), lane = tid & 63, wave = tid >> 6;
+    const int jblk = wave / kWavesG;             // block slot of this wave in the item
+    const int wi = wave % kWavesG;               // wave index within the block
+    const int tib = wi * 64 + lane;              // thread index within the block
+    const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
+    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
+
+    // items of this workgroup: a contiguous range
+    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
+    const int per = (n_items + g.n_wg - 1) / g.n_wg;
+    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+    const int i1 = min(n_items, i0 + per);
+
+    for (int item = i0; item < i1; ++item) {
+        if constexpr (kWavesG == 1) {
+            process_item<T, 0, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+        } else {
+            if (wi == 0) process_item<T, 0, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+            else         process_item<T, 1, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch sequence (all asynchronous on the stream)
+// ---------------------------------------------------------------------------
+
+int group_max_target_samples() { return 64 * 64; }
+
+// Clears the hash table and counters with a kernel (no memset node when a
+// caller captures the launch sequence in a graph).
+__global__ void k_clear(GroupArgs g) {
+    const int i = (int)__builtin_amdgcn_workgroup_id_x() * 256 + (int)__builtin_amdgcn_workitem_id_x();
+    if (i < g.hsize) { g.ht_key[i] = 0ull; g.ht_cnt[i] = 0; }
+    if (i == 0) *g.n_single = 0;
+}
+
+hipError_t launch_clear(const GroupArgs& g, hipStream_t stream) {
+    hipLaunchKernelGGL(k_clear, dim3((g.hsize + 255) / 256), dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
+                          const Timing& tm) {
+    if (p.T != 64) return hipErrorInvalidValue;
+    const hipError_t ew = launch_weights(p, stream);
+    if (ew != hipSuccess) return ew;
+    if (!g.direct) {
+        const int n = p.n_blocks;
+        hipLaunchKernelGGL(k_mask_hash, dim3(n), dim3(64), 0, stream, g);
+        hipLaunchKernelGGL(k_group_count, dim3(n), dim3(64), 0, stream, g);
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, stream, g);
+        hipLaunchKernelGGL(k_group_fill, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
+    }
+    const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
+    int grid = 2 * n_cu;
+    if (grid > max_items) grid = max_items;
+    constexpr int NT = kGroup * kWavesG * 64;
+    const int mn = p.M * p.N;
+    GroupArgs ga = g;
+    ga.n_wg = grid;
+    if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
+    if (mn <= 9 * NT) hipLaunchKernelGGL((fofse_group_kernel<64, 9>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    else              hipLaunchKernelGGL((fofse_group_kernel<64, 16>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
+    return launch_synthesis(p, stream);
+}
+
+}  // namespace fofse

@@ -23,16 +23,55 @@ struct KParams {
     const uint8_t* target;   // [M*N], non-zero on B
     const int32_t* bpix;     // [nB] flat indices m*N+n of B, row-major
     const double* rho_gamma; // [2]
+    double* wtab;            // [M*N] rho_hat ** dist(centre), filled by k_weights
     const double2* twiddle;  // [T] exp(-j 2 pi q / T)
     float* out;              // [n][nB]
-    int32_t* sel;            // [n][K] or null
-    double* coef;            // [n][K][2] or null
+    int32_t* sel;            // [n][K] selection record (caller's or plan workspace)
+    double* coef;            // [n][K][2] coefficient record
     int32_t* status;         // [n] or null
+};
+
+// Blocks per workgroup in the grouped path (they share one W).
+constexpr int kGroup = 4;
+
+// Device workspace and arguments of the grouped path.
+struct GroupArgs {
+    int direct;                       // 1: every block has the complement of B as support
+    int n_wg;                         // workgroups of the persistent main kernel
+    int MN;                           // samples per area
+    const uint8_t* known;             // [n][MN] or null
+    const uint8_t* target;            // [MN]
+    uint32_t hmask;                   // hash table size - 1 (power of two)
+    int hsize;
+    unsigned long long* ht_key;       // [hsize] mask hash | 1, 0 = empty
+    int* ht_rep;                      // [hsize] first block of the class
+    int* ht_cnt;                      // [hsize] blocks in the class
+    int* item_start;                  // [hsize] first work item of the class
+    int* cls;                         // [n] class slot, -1 for a singleton
+    int* pos;                         // [n] position inside the class / singleton index
+    int* n_single;                    // [1]
+    int* counts;                      // [2] grouped items, all items
+    int* item_blk;                    // [n][kGroup] blocks of a work item
+    int* item_n;                      // [n] blocks in the item
+    int* item_cls;                    // [n] class of the item
+};
+
+// Optional events recorded on the stream right before and after the main
+// iteration kernel (null: not recorded).
+struct Timing {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
 };
 
 // Largest number of samples of B a workgroup can hold for FFT size T.
 int max_target_samples(int T);
+int group_max_target_samples();
 
-hipError_t launch_forward(const KParams& p, hipStream_t stream);
+hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm);
+hipError_t launch_synthesis(const KParams& p, hipStream_t stream);
+hipError_t launch_weights(const KParams& p, hipStream_t stream);
+hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
+                          const Timing& tm);
+hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
 
 }  // namespace fofse

@@ -1,0 +1,272 @@
+// The FOFSE iteration for one block whose grid rows 0..T/2 are spread over NW
+// wavefronts (lane = grid column, register slot = grid row), with W in an LDS
+// window; shared by the per-block and the grouped kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "fofse_kernel.h"
+
+namespace fofse {
+
+// ---------------------------------------------------------------------------
+// the per-wave iteration loop
+// ---------------------------------------------------------------------------
+
+template <int T, int NW>
+struct Layout {
+    static constexpr int H = T / 2;
+    static constexpr int Q = T / 4;
+    static constexpr int NROWS = H + 1;
+    static constexpr int WROWS = T + 1;               // window rows -Q .. 3Q
+    static constexpr int NT = NW * 64;
+    // grid rows [begin(w), begin(w+1)) live in wave w
+    __host__ __device__ static constexpr int begin(int w) { return (w * NROWS + NW - 1) / NW; }
+    static constexpr int SMAX = begin(1) - begin(0);
+};
+
+// Row bookkeeping of wave WI: its rows and, for each of the four read forms,
+// the reference row whose window offset is zero (smallest row for a direct
+// form, largest for a mirrored one, so every per-slot offset is >= 0).
+template <int T, int NW, int WI>
+struct WaveRows {
+    using L = Layout<T, NW>;
+    static constexpr int k0 = L::begin(WI);
+    static constexpr int S = L::begin(WI + 1) - k0;
+    static constexpr int k1 = k0 + S - 1;
+    static constexpr int Q = L::Q, H = L::H;
+    static constexpr int r1d = (k1 >= Q) ? (k0 > Q ? k0 : Q) : Q;
+    static constexpr int r1m = (k0 < Q) ? (k1 < Q - 1 ? k1 : Q - 1) : 0;
+    static constexpr int r2d = (k0 <= Q) ? k0 : 0;
+    static constexpr int r2m = (k1 > Q) ? k1 : H;
+};
+
+// Selection key of a bin: the IEEE bits of |R|^2 with the low 12 mantissa bits
+// replaced by (63 - column) * 64 + (63 - row).  As doubles, keys order by
+// magnitude first (the 12 bits change |R|^2 by < 2^-40 relative) and, between
+// equal magnitudes, put the smaller class key column*T + row first -- the
+// oracle's tie rule.  Unused bins get key 0.
+// Residual spectrum of S register slots (re, im per slot) held as chunks of at
+// most 16 doubles, so that a slot chosen at run time (uniform) can be read with
+// GPU register indexing.
+template <int S>
+struct RegSpec {
+    static constexpr int NCH = (S + 15) / 16;
+    static constexpr int CS = (S + NCH - 1) / NCH;
+    typedef double chunk __attribute__((ext_vector_type(CS)));
+    chunk re[NCH], im[NCH];
+    __device__ __forceinline__ double gr(int s) const { return re[s / CS][s % CS]; }
+    __device__ __forceinline__ double gi(int s) const { return im[s / CS][s % CS]; }
+    __device__ __forceinline__ void set(int s, double a, double c) { re[s / CS][s % CS] = a; im[s / CS][s % CS] = c; }
+    // (re, im) of slot s (uniform) in lane `lane` (uniform)
+    __device__ __forceinline__ double2 fetch(int s, int lane) const {
+        const int ch = s / CS, ix = s - ch * CS;
+        double a = 0.0, c = 0.0;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+            if (q == ch) { a = readlane_f64(re[q][ix], lane); c = readlane_f64(im[q][ix], lane); }
+        return make_double2(a, c);
+    }
+};
+
+// One wave's share of the K iterations of one block.  The selection record
+// (class key and coefficient of every iteration) goes to p.sel / p.coef; the
+// model on B is synthesised from it by k_synthesize.  ``live`` = false runs the
+// same barriers without writing (a wave of a missing or flagged block in a
+// workgroup whose waves synchronise every iteration).
+template <int T, int NW, int WI>
+__device__ __forceinline__ void run_wave(RegSpec<WaveRows<T, NW, WI>::S>& R,
+        const double2* win, Xchg<NW>* xchg, const KParams& p, int b, int lane, double gW0,
+        bool live = true) {
+    using L = Layout<T, NW>;
+    using WR = WaveRows<T, NW, WI>;
+    constexpr int S = WR::S;
+    constexpr int H = L::H;
+    constexpr int Q = L::Q;
+    const int K = p.K;
+    const bool lane_ok = lane < T;
+    const bool edge_ok = lane_ok && lane <= H;   // rows 0 and T/2: columns 0..T/2 represent
+    int u = 0, v = 0;
+    double ca = 0.0, cb = 0.0;
+
+    for (int it = 0; it < K; ++it) {
+        // R -= c W[k-u] + conj(c) W[k+u] for every slot, then the slot's key.
+        // Iteration 0 runs with c = 0, which leaves R unchanged.  The window reads
+        // go in chunks of CH slots; the reads of chunk q + 1 are issued before
+        // chunk q is computed (all at once when the wave has few rows).
+        const int l = lane;
+        const int cA = (l - v) & (T - 1), cB = (v - l) & (T - 1);
+        const int cC = (l + v) & (T - 1), cD = (-l - v) & (T - 1);
+        const double2* b1d = win + (WR::r1d - u + Q) * T + cA;
+        const double2* b1m = win + (u - WR::r1m + Q) * T + cB;
+        const double2* b2d = win + (WR::r2d + u + Q) * T + cC;
+        const double2* b2m = win + (T - WR::r2m - u + Q) * T + cD;
+        constexpr int CH = S <= 9 ? S : 2;
+        constexpr int NC = (S + CH - 1) / CH;
+        double2 x1c[CH], x2c[CH], x1n[CH], x2n[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int k = WR::k0 + j;
+            if (j < S) {
+                x1c[j] = (k >= Q) ? b1d[(k - WR::r1d) * T] : b1m[(WR::r1m - k) * T];
+                x2c[j] = (k <= Q) ? b2d[(k - WR::r2d) * T] : b2m[(WR::r2m - k) * T];
+            }
+        }
+        double best = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int s = (q + 1) * CH + j;
+                const int k = WR::k0 + s;
+                if (q + 1 < NC && s < S) {
+                    x1n[j] = (k >= Q) ? b1d[(k - WR::r1d) * T] : b1m[(WR::r1m - k) * T];
+                    x2n[j] = (k <= Q) ? b2d[(k - WR::r2d) * T] : b2m[(WR::r2m - k) * T];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int s = q * CH + j;
+                if (s >= S) break;
+                const int k = WR::k0 + s;
+                const double2 x1 = x1c[j], x2 = x2c[j];
+                // W1 = x1 or conj(x1), W2 = x2 or conj(x2) (mirrored reads)
+                double re = R.gr(s), im = R.gi(s);
+                const double sre = x1.x + x2.x;
+                const double dre = x1.x - x2.x;
+                if (k < Q) {            // W1 = conj(x1), W2 = x2
+                    const double sim = x1.y + x2.y, dim = x2.y - x1.y;
+                    re = fma(-ca, sre, re); re = fma(-cb, sim, re);
+                    im = fma(-ca, dim, im); im = fma(-cb, dre, im);
+                } else if (k == Q) {    // W1 = x1, W2 = x2
+                    const double sim = x1.y + x2.y, dim = x1.y - x2.y;
+                    re = fma(-ca, sre, re); re = fma(cb, dim, re);
+                    im = fma(-ca, sim, im); im = fma(-cb, dre, im);
+                } else {                // W1 = x1, W2 = conj(x2)
+                    const double sim = x1.y + x2.y, dim = x1.y - x2.y;
+                    re = fma(-ca, sre, re); re = fma(cb, sim, re);
+                    im = fma(-ca, dim, im); im = fma(-cb, dre, im);
+                }
+                R.set(s, re, im);
+                // eq. 9: largest |R| over this lane's classes, ties to the smallest row
+                const double m2 = sq_add(im, re * re);
+                uint32_t lo = (__double2loint(m2) & 0xFFFFFFC0u) | (uint32_t)(63 - k);
+                int hi = __double2hiint(m2);
+                if (k == 0 || k == H) { hi = edge_ok ? hi : 0; lo = edge_ok ? lo : 0u; }
+                else if (T < 64)      { hi = lane_ok ? hi : 0; lo = lane_ok ? lo : 0u; }
+                best = max_f64(best, __hiloint2double(hi, (int)lo));
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) { x1c[j] = x1n[j]; x2c[j] = x2n[j]; }
+            if constexpr (NC > 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        // wavefront maximum: high words by DPP; among lanes with equal high words
+        // the larger magnitude bits of the low word, then the smallest lane
+        // (column) -- together with the per-lane row bits this is the order of
+        // the class key column * T + row
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        uint64_t hits = __ballot(bhi == mhi);
+        int wl = __builtin_ctzll(hits);
+        uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)blo, wl);
+        hits &= hits - 1;
+        while (hits) {                       // equal high words in several lanes (rare)
+            const int ln = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const uint32_t l2 = (uint32_t)__builtin_amdgcn_readlane((int)blo, ln);
+            if ((l2 & 0xFFFFFFC0u) > (mlo & 0xFFFFFFC0u)) { mlo = l2; wl = ln; }
+        }
+        mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)mlo);
+        wl = __builtin_amdgcn_readfirstlane(wl);
+        // every wave owns at least one valid bin and valid keys have non-zero
+        // low bits, so the winner is a bin of this wave; the clamp only guards
+        // the register index
+        int wslot = (int)(63 - (mlo & 63u)) - WR::k0;
+        wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
+        const double2 wrv = R.fetch(wslot, wl);
+        const double wre = wrv.x, wim = wrv.y;
+        double2 wv;
+        uint32_t whi, wlo;
+        if constexpr (NW > 1) {
+            Xchg<NW>& x = xchg[it & 1];
+            if (lane == 0) {
+                x.hi[WI] = mhi;
+                // magnitude bits, then (63 - column) and (63 - row) as tie bits
+                x.lo[WI] = (mlo & 0xFFFFF000u) | ((uint32_t)(63 - wl) << 6) | (mlo & 63u);
+                x.val[WI] = make_double2(wre, wim);
+            }
+            __syncthreads();
+            // the candidates of all waves in one broadcast read
+            uint32_t chi[NW], clo[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+            int bw = 0;
+            whi = chi[0];
+            wlo = clo[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
+                bw = gt ? w : bw;
+                whi = gt ? chi[w] : whi;
+                wlo = gt ? clo[w] : wlo;
+            }
+            bw = __builtin_amdgcn_readfirstlane(bw);
+            wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
+            wv = x.val[bw];
+        } else {
+            wlo = (mlo & 0xFFFFF000u) | ((uint32_t)(63 - wl) << 6) | (mlo & 63u);
+            wv = make_double2(wre, wim);
+        }
+        // selected bin: grid row u (the class index l), grid column v (index k)
+        u = 63 - (int)(wlo & 63u);
+        v = (63 - (int)((wlo >> 6) & 63u)) & (T - 1);
+        u = u > H ? H : u;
+        // eqs. 5 and 14: c = gamma R[u] / W0; a self-conjugate class keeps Re c
+        const bool selfc = (u == 0 || u == H) && (v == 0 || v == H);
+        const double cre = wv.x * gW0;
+        const double cim = selfc ? 0.0 : wv.y * gW0;
+        if (live && WI == 0 && lane == 0) {
+            const size_t r = (size_t)b * K + it;
+            p.sel[r] = v * T + u;
+            p.coef[2 * r] = cre;
+            p.coef[2 * r + 1] = cim;
+        }
+        // a self-conjugate class is applied as two half terms (W[k+u] = W[k-u])
+        ca = selfc ? 0.5 * cre : cre;
+        cb = cim;
+    }
+}
+
+
+// eqs. 1, 2: g on the samples of B from the selection record,
+// g = sum over iterations of 2 Re(c phi_{k,l}) (c phi for a self-conjugate class),
+// phi_{k,l}[m, n] = exp(+j 2 pi (k m + l n) / T).  One workgroup per block.
+template <int T>
+__global__ __launch_bounds__(256) void k_synthesize(KParams p) {
+    __shared__ double2 tw[T];
+    const int b = (int)__builtin_amdgcn_workgroup_id_x(), tid = (int)__builtin_amdgcn_workitem_id_x();
+    for (int i = tid; i < T; i += 256) tw[i] = p.twiddle[i];
+    __syncthreads();
+    const int K = p.K, N = p.N, H = T / 2;
+    const int32_t* sel = p.sel + (size_t)b * K;
+    const double* coef = p.coef + 2 * (size_t)b * K;
+    for (int q0 = 0; q0 < p.nB; q0 += 256) {
+        const int q = q0 + tid;
+        const int flat = q < p.nB ? p.bpix[q] : 0;
+        const int m = flat / N, n = flat - m * N;
+        double g = 0.0;
+        for (int it = 0; it < K; ++it) {
+            const int key = sel[it];
+            const int k = key / T, l = key - k * T;
+            const bool selfc = (k == 0 || k == H) && (l == 0 || l == H);
+            const double mult = selfc ? 1.0 : 2.0;
+            const double2 t = tw[(k * m + l * n) & (T - 1)];     // exp(-j ...): Re(c conj(t))
+            g = fma(mult * coef[2 * it], t.x, fma(mult * coef[2 * it + 1], t.y, g));
+        }
+        if (q < p.nB) p.out[(size_t)b * p.nB + q] = (float)g;
+    }
+}
+
+}  // namespace fofse

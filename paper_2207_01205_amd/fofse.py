@@ -27,8 +27,12 @@ FOFSE_BLOCK_NO_SUPPORT = 1
 FOFSE_BLOCK_NONFINITE = 2
 FOFSE_BLOCK_BAD_PARAM = 4
 
-EXPORTED = ("fofse_create", "fofse_target_count", "fofse_extrapolate_batch",
-            "fofse_destroy", "fofse_status_str")
+FOFSE_PATH_AUTO = 0
+FOFSE_PATH_SPLIT = 1
+FOFSE_PATH_GROUPED = 2
+
+EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_extrapolate_batch",
+            "fofse_set_timing", "fofse_kernel_times", "fofse_destroy", "fofse_status_str")
 
 
 class FofseError(RuntimeError):
@@ -60,8 +64,14 @@ def load_library(path: str = LIB_PATH):
     L.fofse_create.restype = ctypes.c_int
     L.fofse_target_count.argtypes = [vp]
     L.fofse_target_count.restype = ctypes.c_int32
+    L.fofse_set_path.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_path.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
+    L.fofse_set_timing.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_timing.restype = ctypes.c_int
+    L.fofse_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    L.fofse_kernel_times.restype = ctypes.c_int32
     L.fofse_destroy.argtypes = [vp]
     L.fofse_destroy.restype = None
     L.fofse_status_str.argtypes = [ctypes.c_int]
@@ -96,6 +106,12 @@ def fofse_target_count(plan: int) -> int:
     return int(load_library().fofse_target_count(plan))
 
 
+def fofse_set_path(plan: int, path: int) -> None:
+    st = load_library().fofse_set_path(plan, int(path))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_path")
+
+
 def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int,
                             d_rho_gamma: int, d_out: int, d_sel: int, d_coef: int,
                             d_status: int, stream: int) -> None:
@@ -106,6 +122,19 @@ def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int
                                                 d_status or None, stream or None)
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_extrapolate_batch")
+
+
+def fofse_set_timing(plan: int, enable: bool) -> None:
+    st = load_library().fofse_set_timing(plan, 1 if enable else 0)
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_timing")
+
+
+def fofse_kernel_times(plan: int, max_count: int = 256):
+    """Main-kernel durations (ms) of the most recent calls, oldest first."""
+    buf = (ctypes.c_float * max_count)()
+    n = load_library().fofse_kernel_times(plan, buf, max_count)
+    return [float(buf[i]) for i in range(n)]
 
 
 def fofse_destroy(plan: int) -> None:
@@ -125,6 +154,9 @@ class Plan:
         self.target_mask = np.asarray(target_mask, dtype=np.uint8).reshape(self.M, self.N)
         self.handle = fofse_create(self.M, self.N, self.T, self.K, self.target_mask, self.device)
         self.nB = fofse_target_count(self.handle)
+
+    def set_path(self, path: int):
+        fofse_set_path(self.handle, path)
 
     def close(self):
         if getattr(self, "handle", None):

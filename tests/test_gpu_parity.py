@@ -22,20 +22,28 @@ TOL_G = 1e-3
 MARGIN = 1e-6
 
 
-def _plan(M, N, T, K, target):
+PATHS = {"split": 1, "grouped": 2}
+
+
+def _plan(M, N, T, K, target, path=None):
     from paper_2207_01205_amd.fofse import Plan
-    return Plan(M, N, T, K, target, device=0)
+    plan = Plan(M, N, T, K, target, device=0)
+    if path is not None:
+        plan.set_path(PATHS[path])
+    return plan
 
 
-def run_gpu(plan, areas, known, rho, gamma, label):
+def run_gpu(plan, areas, known, rho, gamma, label, record=True):
     print(f"[gpu] {label}: n={areas.shape[0]} M={plan.M} N={plan.N} T={plan.T} K={plan.K}",
           flush=True)
     dev = torch.device("cuda", 0)
     a = torch.from_numpy(np.ascontiguousarray(areas, dtype=np.float32)).to(dev)
     k = None if known is None else torch.from_numpy(np.ascontiguousarray(known, dtype=np.uint8)).to(dev)
     rg = torch.tensor([rho, gamma], dtype=torch.float64, device=dev)
-    out, sel, coef, st = plan.extrapolate(a, rg, known=k, record=True)
+    out, sel, coef, st = plan.extrapolate(a, rg, known=k, record=record)
     torch.cuda.synchronize()
+    if not record:
+        return out.cpu().numpy(), None, None, st.cpu().numpy()
     return out.cpu().numpy(), sel.cpu().numpy(), coef.cpu().numpy(), st.cpu().numpy()
 
 
@@ -87,21 +95,23 @@ def frame_areas():
     return synth.frame_concealment(0, 1)
 
 
-def test_frame_blocks_full_iterations(frame_areas):
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_frame_blocks_full_iterations(frame_areas, path):
     A = frame_areas
     sub = slice(0, 96)
-    plan = _plan(48, 48, 64, 200, A.target)
-    out, sel, coef, st = run_gpu(plan, A.areas[sub], A.known[sub], 0.8, 0.5, "frame blocks 0-95")
+    plan = _plan(48, 48, 64, 200, A.target, path)
+    out, sel, coef, st = run_gpu(plan, A.areas[sub], A.known[sub], 0.8, 0.5, f"frame blocks 0-95 {path}")
     ref = oracle_on(A.areas[sub], A.known[sub], A.target, 64, 0.8, 0.5, 200)
     check_parity(ref, A.target, out, sel, coef, st, "frame blocks")
 
 
-def test_full_frame_sampled(frame_areas):
-    """All 804 blocks of the 1080p frame in one launch (the benchmark's launch),
-    checked on a seeded sample of blocks the oracle recomputes one by one."""
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_full_frame_sampled(frame_areas, path):
+    """All 804 blocks of the 1080p frame in one launch, checked on a seeded
+    sample of blocks the oracle recomputes one by one."""
     A = frame_areas
-    plan = _plan(48, 48, 64, 200, A.target)
-    out, sel, coef, st = run_gpu(plan, A.areas, A.known, 0.8, 0.5, "full frame 804 blocks")
+    plan = _plan(48, 48, 64, 200, A.target, path)
+    out, sel, coef, st = run_gpu(plan, A.areas, A.known, 0.8, 0.5, f"full frame 804 blocks {path}")
     idx = np.sort(np.random.default_rng(7).choice(len(A), 40, replace=False))
     ref = oracle_on(A.areas[idx], A.known[idx], A.target, 64, 0.8, 0.5, 200)
     check_parity(ref, A.target, out[idx], sel[idx], coef[idx], st[idx], "full frame sample")
@@ -109,26 +119,30 @@ def test_full_frame_sampled(frame_areas):
     assert np.all(np.isfinite(out))
 
 
-def test_canonical_mask_path(frame_areas):
-    """known = NULL: every block's support is the complement of B."""
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_canonical_mask_path(frame_areas, path):
+    """known = NULL: every block's support is the complement of B (41 blocks:
+    a ragged last group of the grouped path)."""
     A = frame_areas
-    sub = slice(100, 140)
-    plan = _plan(48, 48, 64, 120, A.target)
-    out, sel, coef, st = run_gpu(plan, A.truth[sub], None, 0.9, 0.3, "canonical masks")
+    sub = slice(100, 141)
+    plan = _plan(48, 48, 64, 120, A.target, path)
+    out, sel, coef, st = run_gpu(plan, A.truth[sub], None, 0.9, 0.3, f"canonical masks {path}")
     ref = oracle_on(A.truth[sub], None, A.target, 64, 0.9, 0.3, 120)
     check_parity(ref, A.target, out, sel, coef, st, "canonical masks")
 
 
-def test_off_centre_rectangular_geometry():
-    """Non-square area, off-centre rectangular B, ragged sizes."""
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_off_centre_rectangular_geometry(path):
+    """Non-square area, off-centre rectangular B, random masks (every block
+    its own mask class: the grouped path runs singleton items)."""
     rng = np.random.default_rng(3)
     M, N, T, K = 37, 53, 64, 60
     target = np.zeros((M, N), np.uint8)
     target[5:17, 30:50] = 1
     f = rng.uniform(0, 255, (20, M, N))
     known = (rng.uniform(size=(20, M, N)) < 0.9).astype(np.uint8)
-    plan = _plan(M, N, T, K, target)
-    out, sel, coef, st = run_gpu(plan, f, known, 0.85, 0.6, "off-centre geometry")
+    plan = _plan(M, N, T, K, target, path)
+    out, sel, coef, st = run_gpu(plan, f, known, 0.85, 0.6, f"off-centre geometry {path}")
     ref = oracle_on(f, known, target, T, 0.85, 0.6, K)
     check_parity(ref, target, out, sel, coef, st, "off-centre geometry")
 
@@ -193,10 +207,41 @@ def test_saturated_and_constant_areas():
         assert np.abs(out[i] - f[i].reshape(-1)[tb]).max() <= 1e-9 * 255
 
 
-def test_deterministic(frame_areas):
+def test_edge_cases_grouped():
+    """Status handling of the grouped path (T = 64): a block with no support,
+    a non-finite known sample, a non-finite sample on B, invalid parameters,
+    and blocks sharing a mask class with flagged ones."""
+    A = synth.frame_concealment(2, 3)
+    plan = _plan(48, 48, 64, 80, A.target, "grouped")
+    areas = A.areas[:12].copy()
+    known = A.known[:12].copy()
+    known[3] = 0                                 # no support
+    areas[5, 0, 0] = np.nan
+    known[5, 0, 0] = 1                           # non-finite known sample
+    areas[7, 20, 20] = np.inf                    # on B: ignored
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, "grouped edge cases")
+    expect = np.zeros(12, int)
+    expect[3] = 1
+    expect[5] = 2
+    assert st.tolist() == expect.tolist()
+    assert np.all(out[3] == 0) and np.all(out[5] == 0)
+    assert np.all(sel[3] == 0) and np.all(coef[5] == 0)
+    good = [i for i in range(12) if expect[i] == 0]
+    ref = oracle_on(np.nan_to_num(areas[good], posinf=0.0), known[good], A.target, 64, 0.8, 0.5, 80)
+    check_parity(ref, A.target, out[good], sel[good], coef[good], st[good], "grouped edge cases")
+    out, sel, coef, st = run_gpu(plan, areas[:4], known[:4], 1.5, 0.5, "grouped rho > 1")
+    assert st.tolist() == [4, 4, 4, 4] and np.all(out == 0)
+    # without a caller record the plan keeps its own; outputs are unchanged
+    out2, _, _, _ = run_gpu(plan, A.areas[:12], A.known[:12], 0.8, 0.5, "grouped no record", record=False)
+    out3, _, _, _ = run_gpu(plan, A.areas[:12], A.known[:12], 0.8, 0.5, "grouped with record")
+    assert np.array_equal(out2, out3)
+
+
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_deterministic(frame_areas, path):
     A = frame_areas
-    plan = _plan(48, 48, 64, 200, A.target)
-    r1 = run_gpu(plan, A.areas[:64], A.known[:64], 0.8, 0.5, "determinism run 1")
-    r2 = run_gpu(plan, A.areas[:64], A.known[:64], 0.8, 0.5, "determinism run 2")
+    plan = _plan(48, 48, 64, 200, A.target, path)
+    r1 = run_gpu(plan, A.areas[:64], A.known[:64], 0.8, 0.5, f"determinism run 1 {path}")
+    r2 = run_gpu(plan, A.areas[:64], A.known[:64], 0.8, 0.5, f"determinism run 2 {path}")
     for x, y in zip(r1, r2):
         assert np.array_equal(x, y)
