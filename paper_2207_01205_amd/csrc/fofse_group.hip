@@ -52,8 +52,13 @@ __device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_mask_hash(GroupArgs g) {
-    const int b = (int)__builtin_amdgcn_workgroup_id_x(), lane = (int)__builtin_amdgcn_workitem_id_x();
+// grouping kernels run one wavefront per block, kHashBlocks blocks per workgroup
+constexpr int kHashBlocks = 4;
+
+__global__ __launch_bounds__(64 * kHashBlocks) void k_mask_hash(GroupArgs g, int n) {
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    const int b = (int)__builtin_amdgcn_workgroup_id_x() * kHashBlocks + (tid >> 6), lane = tid & 63;
+    if (b >= n) return;
     const size_t base = (size_t)b * g.MN;
     uint64_t h = 0;
     for (int i = lane; i < g.MN; i += 64)
@@ -71,8 +76,10 @@ __global__ __launch_bounds__(64) void k_mask_hash(GroupArgs g) {
     }
 }
 
-__global__ __launch_bounds__(64) void k_group_count(GroupArgs g) {
-    const int b = (int)__builtin_amdgcn_workgroup_id_x(), lane = (int)__builtin_amdgcn_workitem_id_x();
+__global__ __launch_bounds__(64 * kHashBlocks) void k_group_count(GroupArgs g, int n) {
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    const int b = (int)__builtin_amdgcn_workgroup_id_x() * kHashBlocks + (tid >> 6), lane = tid & 63;
+    if (b >= n) return;
     const int slot = g.cls[b];
     const int rep = g.ht_rep[slot];
     const size_t base = (size_t)b * g.MN, rbase = (size_t)rep * g.MN;
@@ -380,8 +387,9 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
     if (ew != hipSuccess) return ew;
     if (!g.direct) {
         const int n = p.n_blocks;
-        hipLaunchKernelGGL(k_mask_hash, dim3(n), dim3(64), 0, stream, g);
-        hipLaunchKernelGGL(k_group_count, dim3(n), dim3(64), 0, stream, g);
+        const int nwg = (n + kHashBlocks - 1) / kHashBlocks;
+        hipLaunchKernelGGL(k_mask_hash, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
+        hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
         hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, stream, g);
         hipLaunchKernelGGL(k_group_fill, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
     }
