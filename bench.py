@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
-"""FOFSE forward benchmark on one MI355X.
+"""FOFSE forward and forward+adjoint benchmark on one MI355X.
 
 Workload: 1080p frame concealment (the paper's block-loss concealment setting:
 16x16 lost blocks, 16-pixel support frame -> 48x48 areas, 64x64 DFT, rho_hat
 0.8, gamma 0.5, K = 200 iterations), on seeded synthetic 8-bit frames with 10 %
 of the 120 x 67 full macroblocks lost (804 blocks per frame).  One step = one
-forward pass (one launch) over a batch of ``--frames`` frames, inputs resident
-in HBM.  Prints one JSON line.
+forward pass over a batch of ``--frames`` frames, inputs resident in HBM; the
+forward+adjoint step adds the MSE gradient on B against the true pixels and the
+adjoint pass (gradients for the known samples, rho_hat and gamma).  Prints one
+JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
 """
@@ -38,10 +40,19 @@ def flops_per_block(T: int, K: int) -> float:
     return K * 19.0 * classes + 2 * 2.5 * T * T * np.log2(T * T)
 
 
+def adjoint_flops_per_block(T: int, K: int, nB: int) -> float:
+    """Algorithmic FLOP of the adjoint of one block for its selection record:
+    the synthesis transposed (K nB real-by-complex multiply-adds, 4 FLOP), the
+    transposed coefficient recurrence over the K(K-1)/2 iteration pairs (two
+    complex multiply-adds, 16, and the two rho_hat terms, 20), and two T x T
+    FFTs (weights with their rho_hat derivative, and the adjoint spectrum)."""
+    return 4.0 * K * nB + 36.0 * K * (K - 1) / 2 + 2 * 2.5 * T * T * np.log2(T * T)
+
+
 def _frame(i):
     from paper_2207_01205_amd import synth
     a = synth.frame_concealment(i, 1000 + i)
-    return a.areas, a.known, a.target
+    return a.areas, a.known, a.target, a.truth
 
 
 def make_workload(n_frames: int):
@@ -49,7 +60,8 @@ def make_workload(n_frames: int):
         parts = pool.map(_frame, range(n_frames))
     areas = np.concatenate([p[0] for p in parts])
     known = np.concatenate([p[1] for p in parts])
-    return areas, known, parts[0][2]
+    truth = np.concatenate([p[3] for p in parts])
+    return areas, known, parts[0][2], truth
 
 
 def _oracle_chunk(args):
@@ -119,6 +131,7 @@ def main():
     ap.add_argument("--frames", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-single-frame", action="store_true",
                     help="skip the one-frame latency launches (so a profiler's per-kernel "
                          "average covers only full-batch launches)")
@@ -131,7 +144,7 @@ def main():
         sys.exit(2)
 
     # everything that forks runs before the GPU is initialised
-    areas, known, target = make_workload(args.frames)
+    areas, known, target, truth = make_workload(args.frames)
     n = len(areas)
     base = None
     if not args.no_cpu_baseline:
@@ -198,6 +211,53 @@ def main():
         torch.cuda.synchronize()
         t_frame = e0.elapsed_time(e1) * 1e-3 / 5
 
+    # forward + adjoint: MSE on B against the true pixels, gradients for the
+    # known samples, rho_hat and gamma (the forward's record feeds the adjoint)
+    adj = None
+    if not args.no_adjoint:
+        tb = target.reshape(-1) == 1
+        d_truth = torch.from_numpy(np.ascontiguousarray(truth.reshape(n, -1)[:, tb])).to(dev)
+        gout = torch.empty_like(out)
+        gareas = torch.empty_like(d_areas)
+        grg = torch.empty((2,), dtype=torch.float64, device=dev)
+        gblk = torch.empty((n, 2), dtype=torch.float64, device=dev)
+
+        def step_adj():
+            step()
+            torch.sub(out, d_truth, out=gout)
+            gout.mul_(2.0 / gout.numel())
+            F.fofse_backward(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(), rg.data_ptr(),
+                             sel.data_ptr(), coef.data_ptr(), gout.data_ptr(), gareas.data_ptr(),
+                             grg.data_ptr(), gblk.data_ptr(), stream.cuda_stream)
+
+        for _ in range(args.warmup):
+            step_adj()
+        torch.cuda.synchronize()
+        F.fofse_set_timing(plan.handle, True)   # forward and adjoint kernels alternate in the ring
+        ea = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ea[0].record(stream)
+        for _ in range(args.steps):
+            step_adj()
+        ea[1].record(stream)
+        torch.cuda.synchronize()
+        times = F.fofse_kernel_times(plan.handle, 2 * args.steps)
+        F.fofse_set_timing(plan.handle, False)
+        t_adj = ea[0].elapsed_time(ea[1]) * 1e-3
+        bwd_k = float(np.mean(times[1::2])) * 1e-3
+        fab = adjoint_flops_per_block(T, K, plan.nB)
+        fpb_all = flops_per_block(T, K) + fab
+        adj = {"value": n * args.steps / t_adj, "unit": "blocks/s",
+               "ms_per_step": t_adj / args.steps * 1e3,
+               "fp32_vector_peak_frac": fpb_all * n * args.steps / t_adj / FP32_VECTOR_PEAK,
+               "adjoint_kernel": {"kernel": "fofse_bwd_kernel<64,256>", "flop_per_block": fab,
+                                  "avg_launch_ms": bwd_k * 1e3,
+                                  "achieved": fab * n / bwd_k / 1e12, "unit": "TFLOP/s",
+                                  "peak": FP64_VECTOR_PEAK / 1e12,
+                                  "frac": fab * n / bwd_k / FP64_VECTOR_PEAK},
+               "grad_rho_gamma": [float(x) for x in grg.cpu().numpy()]}
+        print(f"[bench] fwd+adjoint: {t_adj / args.steps * 1e3:.3f} ms per step, adjoint kernel "
+              f"{bwd_k * 1e3:.3f} ms", file=sys.stderr, flush=True)
+
     # final full-batch pass for the outputs checked below
     step()
     torch.cuda.synchronize()
@@ -235,6 +295,7 @@ def main():
                      "kernel": kname, "flop_per_block": fpb,
                      "avg_launch_ms": kern * 1e3, "avg_step_ms": float(np.mean(per_step)) * 1e3},
         "block_status_nonzero": int(np.count_nonzero(status)),
+        "fwd_adjoint": adj,
     }
     if base is not None:
         info, ref = base

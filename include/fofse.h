@@ -143,9 +143,10 @@ fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
                                      int32_t* d_status, void* stream);
 
 /*
- * Profiling hook.  With timing enabled, every fofse_extrapolate_batch call
- * records a pair of HIP events on its stream around its main kernel (the
- * iteration kernel; the weight, grouping and synthesis kernels are outside).
+ * Profiling hook.  With timing enabled, every fofse_extrapolate_batch and
+ * fofse_backward call records a pair of HIP events on its stream around its
+ * main kernel (the iteration kernel, or the adjoint kernel; the weight,
+ * grouping, synthesis and summation kernels are outside).
  * The plan keeps the pairs of the last 256 calls.
  *   fofse_set_timing    enable (non-zero) or disable; enabling clears the ring.
  *                       FOFSE_ERR_ARG for a NULL plan, FOFSE_ERR_DEVICE if the
@@ -158,6 +159,48 @@ fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
  */
 fofse_status fofse_set_timing(fofse_plan plan, int32_t enable);
 int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
+
+/*
+ * Adjoint of fofse_extrapolate_batch with the selection held fixed.
+ *
+ * The paper does not differentiate the extrapolation; this is the exact
+ * derivative of the forward steps (eqs. 1-5, 7, 8, 14, 15) for the classes
+ * recorded by a forward call.  Given that record the model g on B is linear in
+ * the known samples f, and smooth in rho_hat and gamma.  For a loss L with
+ * dL/dg = d_grad_out it returns dL/df, dL/drho_hat and dL/dgamma.  Arithmetic is
+ * IEEE double precision on the device.
+ *
+ *   d_areas, d_known, d_rho_gamma : the forward call's inputs (same layout and
+ *                    meaning as in fofse_extrapolate_batch).
+ *   d_sel, d_coef  : device int32 [n_blocks][K] and double [n_blocks][K][2], the
+ *                    record written by the forward call on these inputs (class
+ *                    keys u*T+v and coefficients c).  Keys are read modulo the
+ *                    grid, so any key yields a defined result.
+ *   d_grad_out     : device float [n_blocks][nB], dL/dg on the samples of B
+ *                    (layout of the forward's d_out).
+ *   d_grad_areas   : device float [n_blocks][M*N] or NULL: dL/df, 0 off the
+ *                    support area A.
+ *   d_grad_rho_gamma : device double [2] or NULL: {dL/drho_hat, dL/dgamma}
+ *                    summed over the blocks in a fixed order (overwritten, not
+ *                    accumulated).
+ *   d_grad_block   : device double [n_blocks][2] or NULL: the same per block.
+ *   stream         : hipStream_t (as void*), NULL for the null stream.
+ *
+ * Blocks whose forward status would be non-zero (non-finite known sample,
+ * W0 <= 0, rho_hat or gamma out of range) get zero gradients.
+ * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
+ * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
+ * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, FOFSE_ERR_NOMEM if the per-block
+ * workspace (16 B per block, used when d_grad_block is NULL) cannot be
+ * allocated, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
+ * n_blocks == 0 is a no-op (d_grad_rho_gamma is not written).
+ */
+fofse_status fofse_backward(fofse_plan plan, int32_t n_blocks,
+                            const float* d_areas, const uint8_t* d_known,
+                            const double* d_rho_gamma, const int32_t* d_sel,
+                            const double* d_coef, const float* d_grad_out,
+                            float* d_grad_areas, double* d_grad_rho_gamma,
+                            double* d_grad_block, void* stream);
 
 /* Release the plan and its device memory.  NULL is ignored. */
 void fofse_destroy(fofse_plan plan);

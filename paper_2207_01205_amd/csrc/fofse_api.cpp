@@ -21,6 +21,10 @@ struct fofse_plan_s {
     int32_t* d_bpix = nullptr;
     double2* d_twiddle = nullptr;
     double* d_wtab = nullptr;       // rho_hat ** dist per sample, refreshed per call
+    double* d_dwtab = nullptr;      // its derivative in rho_hat (adjoint only)
+    // per-block gradients when the caller passes no d_grad_block
+    int gblk_blocks = 0;
+    double* d_gblk = nullptr;
     // grouped-path workspace, grown on demand (capacity in blocks)
     int ws_blocks = 0;
     int ws_hsize = 0;
@@ -77,6 +81,8 @@ void free_plan(fofse_plan p) {
     if (p->d_bpix) (void)hipFree(p->d_bpix);
     if (p->d_twiddle) (void)hipFree(p->d_twiddle);
     if (p->d_wtab) (void)hipFree(p->d_wtab);
+    if (p->d_dwtab) (void)hipFree(p->d_dwtab);
+    if (p->d_gblk) (void)hipFree(p->d_gblk);
     delete p;
 }
 
@@ -187,7 +193,8 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     if (hipMalloc(&p->d_target, M * N) != hipSuccess ||
         hipMalloc(&p->d_bpix, bpix.size() * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_twiddle, T * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->d_wtab, (size_t)M * N * sizeof(double)) != hipSuccess) {
+        hipMalloc(&p->d_wtab, (size_t)M * N * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_dwtab, (size_t)M * N * sizeof(double)) != hipSuccess) {
         free_plan(p);
         return FOFSE_ERR_NOMEM;
     }
@@ -303,6 +310,61 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
     } else {
         e = fofse::launch_forward(k, st, tm);
     }
+    return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
+}
+
+fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas,
+                            const uint8_t* d_known, const double* d_rho_gamma,
+                            const int32_t* d_sel, const double* d_coef, const float* d_grad_out,
+                            float* d_grad_areas, double* d_grad_rho_gamma, double* d_grad_block,
+                            void* stream) {
+    if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
+    if (n_blocks == 0) return FOFSE_OK;
+    if (!d_areas || !d_rho_gamma || !d_sel || !d_coef || !d_grad_out) return FOFSE_ERR_ARG;
+    if (p->K > fofse::kBackwardMaxK) return FOFSE_ERR_UNSUPPORTED;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return FOFSE_ERR_DEVICE;
+    double* blk = d_grad_block;
+    if (!blk) {
+        if (n_blocks > p->gblk_blocks) {
+            if (p->d_gblk) (void)hipFree(p->d_gblk);
+            p->d_gblk = nullptr;
+            p->gblk_blocks = 0;
+            if (hipMalloc(&p->d_gblk, (size_t)n_blocks * 2 * sizeof(double)) != hipSuccess)
+                return FOFSE_ERR_NOMEM;
+            p->gblk_blocks = n_blocks;
+        }
+        blk = p->d_gblk;
+    }
+    fofse::KParams wp{};
+    wp.T = p->T; wp.M = p->M; wp.N = p->N; wp.K = p->K; wp.nB = p->nB;
+    wp.rho_gamma = d_rho_gamma;
+    wp.wtab = p->d_wtab;
+    wp.dwtab = p->d_dwtab;
+    fofse::BParams b{};
+    b.n_blocks = n_blocks;
+    b.T = p->T; b.M = p->M; b.N = p->N; b.K = p->K; b.nB = p->nB;
+    b.areas = d_areas;
+    b.known = d_known;
+    b.target = p->d_target;
+    b.bpix = p->d_bpix;
+    b.rho_gamma = d_rho_gamma;
+    b.wtab = p->d_wtab;
+    b.dwtab = p->d_dwtab;
+    b.twiddle = p->d_twiddle;
+    b.sel = d_sel;
+    b.coef = d_coef;
+    b.grad_out = d_grad_out;
+    b.grad_areas = d_grad_areas;
+    b.grad_block = blk;
+    fofse::Timing tm{};
+    if (p->timing) {
+        const int i = (int)(p->n_timed % kRing);
+        tm.start = p->ev_start[i];
+        tm.stop = p->ev_stop[i];
+        ++p->n_timed;
+    }
+    const hipError_t e = fofse::launch_backward(wp, b, d_grad_rho_gamma, (hipStream_t)stream, tm);
     return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
 }
 

@@ -194,7 +194,11 @@ __global__ __launch_bounds__(256) void k_weights(KParams p) {
     const int m = i / p.N, n = i - m * p.N;
     const double dm = m - 0.5 * (p.M - 1), dn = n - 0.5 * (p.N - 1);
     const double rho = p.rho_gamma[0];
-    p.wtab[i] = param_ok(rho) ? pow(rho, sqrt(dm * dm + dn * dn)) : 0.0;
+    const bool ok = param_ok(rho);
+    const double d = sqrt(dm * dm + dn * dn);
+    p.wtab[i] = ok ? pow(rho, d) : 0.0;
+    // derivative d rho^(d-1) for the adjoint (0 at the centre sample, d = 0)
+    if (p.dwtab) p.dwtab[i] = ok && d > 0.0 ? d * pow(rho, d - 1.0) : 0.0;
 }
 
 hipError_t launch_weights(const KParams& p, hipStream_t stream) {

@@ -24,12 +24,35 @@ struct KParams {
     const int32_t* bpix;     // [nB] flat indices m*N+n of B, row-major
     const double* rho_gamma; // [2]
     double* wtab;            // [M*N] rho_hat ** dist(centre), filled by k_weights
+    double* dwtab;           // [M*N] d/drho_hat of wtab, or null (not needed)
     const double2* twiddle;  // [T] exp(-j 2 pi q / T)
     float* out;              // [n][nB]
     int32_t* sel;            // [n][K] selection record (caller's or plan workspace)
     double* coef;            // [n][K][2] coefficient record
     int32_t* status;         // [n] or null
 };
+
+// Arguments of the adjoint (backward) kernels.
+struct BParams {
+    int n_blocks;
+    int T, M, N, K, nB;
+    const float* areas;      // [n][M*N]
+    const uint8_t* known;    // [n][M*N] or null
+    const uint8_t* target;   // [M*N]
+    const int32_t* bpix;     // [nB]
+    const double* rho_gamma; // [2]
+    const double* wtab;      // [M*N] rho_hat ** dist
+    const double* dwtab;     // [M*N] dist * rho_hat ** (dist - 1)
+    const double2* twiddle;  // [T] exp(-j 2 pi q / T)
+    const int32_t* sel;      // [n][K] forward record: class keys
+    const double* coef;      // [n][K][2] forward record: coefficients
+    const float* grad_out;   // [n][nB] dL/dg on B
+    float* grad_areas;       // [n][M*N] dL/df, or null
+    double* grad_block;      // [n][2] per-block (dL/drho_hat, dL/dgamma)
+};
+
+// Largest K the adjoint kernel holds in LDS.
+constexpr int kBackwardMaxK = 2048;
 
 // Blocks per workgroup in the grouped path (they share one W).
 constexpr int kGroup = 4;
@@ -73,5 +96,7 @@ hipError_t launch_weights(const KParams& p, hipStream_t stream);
 hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
                           const Timing& tm);
 hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
+hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
+                           const Timing& tm);
 
 }  // namespace fofse

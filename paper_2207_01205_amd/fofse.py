@@ -32,7 +32,10 @@ FOFSE_PATH_SPLIT = 1
 FOFSE_PATH_GROUPED = 2
 
 EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_extrapolate_batch",
-            "fofse_set_timing", "fofse_kernel_times", "fofse_destroy", "fofse_status_str")
+            "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
+            "fofse_status_str")
+
+BACKWARD_MAX_K = 2048
 
 
 class FofseError(RuntimeError):
@@ -68,6 +71,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_set_path.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
+    L.fofse_backward.argtypes = [vp, ctypes.c_int32] + [vp] * 10
+    L.fofse_backward.restype = ctypes.c_int
     L.fofse_set_timing.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_timing.restype = ctypes.c_int
     L.fofse_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
@@ -122,6 +127,19 @@ def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int
                                                 d_status or None, stream or None)
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_extrapolate_batch")
+
+
+def fofse_backward(plan: int, n_blocks: int, d_areas: int, d_known: int, d_rho_gamma: int,
+                   d_sel: int, d_coef: int, d_grad_out: int, d_grad_areas: int,
+                   d_grad_rho_gamma: int, d_grad_block: int, stream: int) -> None:
+    """Raw call with device addresses (ints, 0 for NULL); raises FofseError."""
+    st = load_library().fofse_backward(plan, int(n_blocks), d_areas or None, d_known or None,
+                                       d_rho_gamma or None, d_sel or None, d_coef or None,
+                                       d_grad_out or None, d_grad_areas or None,
+                                       d_grad_rho_gamma or None, d_grad_block or None,
+                                       stream or None)
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_backward")
 
 
 def fofse_set_timing(plan: int, enable: bool) -> None:
@@ -203,6 +221,36 @@ class Plan:
                                 st.data_ptr() if st is not None else 0,
                                 stream.cuda_stream)
         return out, sel, coef, st
+
+
+    def backward(self, areas, rho_gamma, sel, coef, grad_out, known=None,
+                 grad_areas: bool = True, per_block: bool = False, stream=None):
+        """Adjoint of :meth:`extrapolate` for its record (sel, coef).
+
+        grad_out: cuda float32 [n, nB] = dL/dg on B.  Returns (grad_areas
+        float32 [n, M, N] or None, grad_rho_gamma float64 [2] summed over the
+        blocks, grad_block float64 [n, 2] or None), enqueued on ``stream``."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = int(areas.shape[0])
+        _check(areas, torch.float32, (n, self.M, self.N), dev, "areas")
+        _check(rho_gamma, torch.float64, (2,), dev, "rho_gamma")
+        _check(sel, torch.int32, (n, self.K), dev, "sel")
+        _check(coef, torch.float64, (n, self.K, 2), dev, "coef")
+        _check(grad_out, torch.float32, (n, self.nB), dev, "grad_out")
+        if known is not None:
+            _check(known, torch.uint8, (n, self.M, self.N), dev, "known")
+        ga = torch.empty((n, self.M, self.N), dtype=torch.float32, device=dev) if grad_areas else None
+        grg = torch.zeros((2,), dtype=torch.float64, device=dev)
+        gb = torch.empty((n, 2), dtype=torch.float64, device=dev) if per_block else None
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        fofse_backward(self.handle, n, areas.data_ptr(),
+                       known.data_ptr() if known is not None else 0,
+                       rho_gamma.data_ptr(), sel.data_ptr(), coef.data_ptr(), grad_out.data_ptr(),
+                       ga.data_ptr() if ga is not None else 0, grg.data_ptr(),
+                       gb.data_ptr() if gb is not None else 0, stream.cuda_stream)
+        return ga, grg, gb
 
 
 def _check(t, dtype, shape, dev, name):
