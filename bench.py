@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the workload, copy MIB MiB once with a plain device copy, so "
+                         "that a counter run can scale FETCH_SIZE / WRITE_SIZE by known bytes")
     ap.add_argument("--no-single-frame", action="store_true",
                     help="skip the one-frame latency launches (so a profiler's per-kernel "
                          "average covers only full-batch launches)")
@@ -166,6 +169,14 @@ def main():
     coef = torch.empty((n, K, 2), dtype=torch.float64, device=dev)
     st = torch.empty((n,), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones((nbytes // 4,), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] calibration copy of {nbytes} bytes", file=sys.stderr, flush=True)
 
     from paper_2207_01205_amd import fofse as F
 

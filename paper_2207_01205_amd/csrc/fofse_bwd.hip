@@ -63,19 +63,39 @@ struct Key {
     }
 };
 
-// W[k] = (Z[k] + conj Z[-k]) / 2 from Z = W + j D (FFT output order in LDS)
+// Byte offsets of Z[u_j - u_i], Z[u_i - u_j], Z[u_j + u_i], Z[-u_j - u_i] in the
+// LDS spectrum, for a per-lane class u_i = (ku, lu) and a uniform u_j.
+// T = 64: Z in natural order; the two indices travel packed as k << 8 | l with
+// a guard bit (128) that keeps the l field from borrowing, so each offset is
+// one add or subtract and three bit operations.  Other T: FFT output order.
 template <int T>
-__device__ __forceinline__ double2 w_at(const double2* Z, int k, int l) {
-    const double2 a = Z[zp<T>(k, l)], b = Z[zp<T>(-k, -l)];
-    return make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-}
+struct ZOff {
+    int ku, lu;
+    __device__ ZOff(int k, int l) : ku(k), lu(l) {}
+    __device__ void get(int kj, int lj, int& a, int& b, int& c, int& d) const {
+        a = 16 * zp<T>(kj - ku, lj - lu);
+        b = 16 * zp<T>(ku - kj, lu - lj);
+        c = 16 * zp<T>(kj + ku, lj + lu);
+        d = 16 * zp<T>(-kj - ku, -lj - lu);
+    }
+};
 
-// W[k] and D[k] = (Z[k] - conj Z[-k]) / (2j)
-template <int T>
-__device__ __forceinline__ void wd_at(const double2* Z, int k, int l, double2& W, double2& D) {
-    const double2 a = Z[zp<T>(k, l)], b = Z[zp<T>(-k, -l)];
-    W = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-    D = make_double2(0.5 * (a.y + b.y), 0.5 * (b.x - a.x));
+template <>
+struct ZOff<64> {
+    int yd, ym;
+    __device__ ZOff(int k, int l) : yd((k << 8) | l), ym((k << 8) | 128 | l) {}
+    __device__ static int off(int r) { return ((r << 2) & 0xFC00) | ((r << 4) & 0x3F0); }
+    __device__ void get(int kj, int lj, int& a, int& b, int& c, int& d) const {
+        const int xs = (kj << 8) | lj;
+        a = off((xs | 128) - yd);
+        b = off(ym - xs);
+        c = off(xs + yd);
+        d = off(((64 << 8) | 128) - xs - yd);
+    }
+};
+
+__device__ __forceinline__ double2 lds_at(const double2* base, int byte_off) {
+    return *(const double2*)((const char*)base + byte_off);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -87,7 +107,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }  // namespace
 
 template <int T, int KMAX>
-__global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
+__global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BParams p) {
     constexpr int NT = 256;
     constexpr int CH = 256;                 // samples of B staged per pass
     using KY = Key<T>;
@@ -96,8 +116,7 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     __shared__ int keyL[KMAX];
     __shared__ double2 cL[KMAX];
     __shared__ double2 cbL[KMAX];
-    __shared__ float gq[CH];
-    __shared__ int mnq[CH];
+    __shared__ int2 gm[CH];                 // (dL/dg as float bits, m << 16 | n)
     __shared__ double red[2][NT / 64];
     __shared__ int s_flags;
 
@@ -113,29 +132,47 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     for (int i = tid; i < T * T; i += NT) buf[i] = make_double2(0.0, 0.0);
     const size_t rb = (size_t)b * K;
     for (int i = tid; i < K; i += NT) {
-        keyL[i] = p.sel[rb + i];
+        keyL[i] = p.sel[rb + i] & (T * T - 1);     // k * T + l, read modulo the grid
         cL[i] = make_double2(p.coef[2 * (rb + i)], p.coef[2 * (rb + i) + 1]);
     }
     if (tid == 0) s_flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
 
-    // z = w + j dw/drho on the T x T grid, area at the origin (row m, column n)
+    // z = w + j dw/drho on the T x T grid, area at the origin (row m, column n);
+    // all loads of a thread are issued before the first use
+    constexpr int PPT = T * T / NT;         // samples per thread (M N <= T^2)
     const size_t ab = (size_t)b * MN;
-    for (int i = tid; i < MN; i += NT) {
-        const int m = i / N, n = i - m * N;
-        bool a = p.target[i] == 0;
-        if (p.known) a = a && p.known[ab + i] != 0;
-        double w = 0.0, dw = 0.0;
-        if (a) {
-            const float fv = p.areas[ab + i];
-            if ((__float_as_uint(fv) & 0x7f800000u) == 0x7f800000u) {
-                atomicOr(&s_flags, FOFSE_BLOCK_NONFINITE);
-            } else {
-                w = p.wtab[i];
-                dw = p.dwtab[i];
+    {
+        bool a[PPT];
+        float fv[PPT];
+        double w[PPT], dw[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int i = tid + j * NT;
+            a[j] = false;
+            fv[j] = 0.0f;
+            w[j] = dw[j] = 0.0;
+            if (i < MN) {
+                a[j] = p.target[i] == 0 && (!p.known || p.known[ab + i] != 0);
+                fv[j] = p.areas[ab + i];
+                w[j] = p.wtab[i];
+                dw[j] = p.dwtab[i];
             }
         }
-        buf[m * T + n] = make_double2(w, dw);
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int i = tid + j * NT;
+            if (i < MN) {
+                const int m = i / N, n = i - m * N;
+                // exponent all ones = Inf or NaN (tested on the bits)
+                const bool nf = (__float_as_uint(fv[j]) & 0x7f800000u) == 0x7f800000u;
+                bad |= a[j] && nf;
+                const bool use = a[j] && !nf;
+                buf[m * T + n] = use ? make_double2(w[j], dw[j]) : make_double2(0.0, 0.0);
+            }
+        }
+        if (bad) atomicOr(&s_flags, FOFSE_BLOCK_NONFINITE);
     }
     __syncthreads();
     fft_stage_a<T, NT>(buf, tw, M, T, 1, tid);
@@ -146,6 +183,19 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     __syncthreads();
     fft_stage_b<T, NT>(buf, T, 1, T, tid);
     __syncthreads();
+    if constexpr (T == 64) {
+        // FFT output order -> natural order.  For T = 64 the order swaps the
+        // two octal digits of each index, an involution: one pass of swaps.
+        for (int e = tid; e < T * T; e += NT) {
+            const int pe = FftPlan<T>::perm(e / T) * T + FftPlan<T>::perm(e % T);
+            if (pe > e) {
+                const double2 x = buf[e], y = buf[pe];
+                buf[e] = y;
+                buf[pe] = x;
+            }
+        }
+        __syncthreads();
+    }
     const double W0 = buf[0].x, dW0 = buf[0].y;
     int flags = s_flags;
     if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
@@ -160,32 +210,41 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     }
     const double gW = gamma / W0;
 
-    // cbar0_nu = mult Gbar[u_nu], Gbar[k] = sum_B gbar[x] exp(-j 2 pi <k, x> / T)
+    // cbar0_nu = mult Gbar[u_nu], Gbar[k] = sum_B gbar[x] exp(-j 2 pi <k, x> / T);
+    // the samples of B are staged through LDS (padded with zeros to a
+    // multiple of 8, so the unrolled loop needs no tail)
     for (int nu0 = 0; nu0 < K; nu0 += NT) {
         const int nu = nu0 + tid;
-        int k = 0, l = 0;
-        if (nu < K) {
-            const int key = keyL[nu];
-            k = KY::k(key);
-            l = KY::l(key);
-        }
+        const int key = nu < K ? keyL[nu] : 0;
+        const int k = KY::k(key), l = KY::l(key);
         double ar = 0.0, ai = 0.0;
         for (int q0 = 0; q0 < nB; q0 += CH) {
             const int cnt = min(CH, nB - q0);
+            const int cnt8 = (cnt + 7) & ~7;
             __syncthreads();
-            for (int i = tid; i < cnt; i += NT) {
-                const int flat = p.bpix[q0 + i];
-                const int m = flat / N, n = flat - m * N;
-                gq[i] = p.grad_out[(size_t)b * nB + q0 + i];
-                mnq[i] = (m << 16) | n;
+            for (int i = tid; i < cnt8; i += NT) {
+                int2 v = make_int2(0, 0);
+                if (i < cnt) {
+                    const int flat = p.bpix[q0 + i];
+                    const int m = flat / N, n = flat - m * N;
+                    v = make_int2(__float_as_int(p.grad_out[(size_t)b * nB + q0 + i]), (m << 16) | n);
+                }
+                gm[i] = v;
             }
             __syncthreads();
-            for (int i = 0; i < cnt; ++i) {
-                const int mn = mnq[i];
-                const double2 t = tw[(k * (mn >> 16) + l * (mn & 0xFFFF)) & (T - 1)];
-                const double g = (double)gq[i];
-                ar = fma(g, t.x, ar);
-                ai = fma(g, t.y, ai);
+            for (int i = 0; i < cnt8; i += 8) {
+                int2 v[8];
+                double2 t[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = gm[i + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t[u] = tw[(k * (v[u].y >> 16) + l * (v[u].y & 0xFFFF)) & (T - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double g = (double)__int_as_float(v[u].x);
+                    ar = fma(g, t[u].x, ar);
+                    ai = fma(g, t[u].y, ai);
+                }
             }
         }
         if (nu < K)
@@ -193,81 +252,128 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     }
     __syncthreads();
 
-    // transposed recurrence, panels of 64 iterations from the last
+    // transposed recurrence, panels of P iterations from the last
+    constexpr int P = 16;
+    const double hW = 0.5 * gW;         // sbar / 2 absorbs the halving in W = (Z + conj Z(-k)) / 2
     double racc = 0.0;
-    for (int pn = (K - 1) >> 6; pn >= 0; --pn) {
-        const int base = pn << 6, cnt = min(64, K - base), hi = base + cnt;
+    for (int pn = (K - 1) / P; pn >= 0; --pn) {
+        const int base = pn * P, cnt = min(P, K - base), hi = base + cnt;
         if (wave == 0) {
-            const int nu = base + lane;
+            // lanes 0..cnt-1 = iterations base..hi-1.  Each lane first takes the
+            // W samples it needs from every later iteration of the panel into
+            // registers; the serial sweep then touches no memory: the finished
+            // adjoint of iteration j reaches the other lanes by readlane.
             const bool valid = lane < cnt;
-            int ku = 0, lu = 0;
-            bool pr = false;
-            double2 cb = make_double2(0.0, 0.0);
-            if (valid) {
-                const int key = keyL[nu];
-                ku = KY::k(key);
-                lu = KY::l(key);
-                pr = KY::pair(ku, lu);
-                cb = cbL[nu];
+            const int key = valid ? keyL[base + lane] : 0;
+            const int ku = KY::k(key), lu = KY::l(key);
+            const bool pr = KY::pair(ku, lu);
+            double2 cb = valid ? cbL[base + lane] : make_double2(0.0, 0.0);
+            double wr[P], wi[P], vr[P], vi[P];     // 2 W[u_j - u_i], 2 W[u_j + u_i]
+            if (lane < P) {
+                const ZOff<T> zo(ku, lu);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int jj = min(j, cnt - 1);
+                    const int kj = __builtin_amdgcn_readlane(ku, jj), lj = __builtin_amdgcn_readlane(lu, jj);
+                    int oa, ob, oc, od;
+                    zo.get(kj, lj, oa, ob, oc, od);
+                    const double2 za = lds_at(buf, oa), zb = lds_at(buf, ob);
+                    const double2 zc = lds_at(buf, oc), zd = lds_at(buf, od);
+                    wr[j] = za.x + zb.x;
+                    wi[j] = za.y - zb.y;
+                    vr[j] = zc.x + zd.x;
+                    vi[j] = zc.y - zd.y;
+                }
             }
-            for (int j = cnt - 1; j >= 0; --j) {
-                const int keyj = keyL[base + j];
-                const int kj = KY::k(keyj), lj = KY::l(keyj);
-                const double cr = readlane_f64(cb.x, j);
-                const double ci = KY::pair(kj, lj) ? readlane_f64(cb.y, j) : 0.0;
-                if (lane == j) cb = make_double2(cr, ci);          // final adjoint of c_j
-                const double sr = gW * cr, si = gW * ci;           // sbar_j
-                if (lane < j) {
-                    const double2 wd = w_at<T>(buf, kj - ku, lj - lu);
-                    cb.x -= sr * wd.x + si * wd.y;                  // sbar conj(W[u_j - u_i])
-                    cb.y -= si * wd.x - sr * wd.y;
-                    if (pr) {
-                        const double2 ws = w_at<T>(buf, kj + ku, lj + lu);
-                        cb.x -= sr * ws.x + si * ws.y;              // conj(sbar) W[u_j + u_i]
-                        cb.y -= sr * ws.y - si * ws.x;
+#pragma unroll
+            for (int j = P - 1; j >= 0; --j) {
+                if (j < cnt) {
+                    const int keyj = __builtin_amdgcn_readlane(key, j);
+                    const bool pj = KY::pair(KY::k(keyj), KY::l(keyj));
+                    const double cr = readlane_f64(cb.x, j);
+                    const double ci = pj ? readlane_f64(cb.y, j) : 0.0;
+                    if (lane == j) cb = make_double2(cr, ci);      // final adjoint of c_j
+                    const double sr = hW * cr, si = hW * ci;       // sbar_j / 2
+                    if (lane < j) {
+                        cb.x -= sr * wr[j] + si * wi[j];            // sbar conj(W[u_j - u_i])
+                        cb.y -= si * wr[j] - sr * wi[j];
+                        if (pr) {
+                            cb.x -= sr * vr[j] + si * vi[j];        // conj(sbar) W[u_j + u_i]
+                            cb.y -= sr * vi[j] - si * vr[j];
+                        }
                     }
                 }
             }
-            if (valid) cbL[nu] = cb;
+            if (valid) cbL[base + lane] = cb;
         }
         __syncthreads();
-        // the panel's sbar into the earlier iterations, and the rho terms of
-        // every pair (mu < nu) with nu in this panel
-        for (int mu = tid; mu < hi; mu += NT) {
+        // The panel's sbar into the earlier iterations (mu < base), and the
+        // rho terms of every pair mu < nu with nu in the panel.  G threads
+        // (adjacent lanes) share the panel's iterations of one mu, so that
+        // about hi * P pairs spread over the workgroup; their partial sums
+        // meet by butterfly shuffles (fixed order).
+        const int G = hi <= 16 ? 16 : hi <= 32 ? 8 : hi <= 64 ? 4 : hi <= 128 ? 2 : 1;
+        const int NQ = P / G;
+        for (int t = tid; t < hi * G; t += NT) {
+            const int mu = t / G, g = t - mu * G;
             const int key = keyL[mu];
             const int ku = KY::k(key), lu = KY::l(key);
             const bool pr = KY::pair(ku, lu);
             const bool cross = mu < base;
             const double2 c = cL[mu];
+            const ZOff<T> zo(ku, lu);
             double ar = 0.0, ai = 0.0, rr = 0.0;
-            for (int nu = max(base, mu + 1); nu < hi; ++nu) {
-                const int key2 = keyL[nu];
-                const int kn = KY::k(key2), ln = KY::l(key2);
-                const double2 cbn = cbL[nu];
-                const double sr = gW * cbn.x, si = gW * cbn.y;
-                double2 Wd, Dd;
-                wd_at<T>(buf, kn - ku, ln - lu, Wd, Dd);
-                if (cross) {
-                    ar -= sr * Wd.x + si * Wd.y;
-                    ai -= si * Wd.x - sr * Wd.y;
+            for (int q0 = 0; q0 < NQ; q0 += 4) {
+                double sr[4], si[4];
+                double2 za[4], zb[4], zc[4], zd[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int nu = base + g + (q0 + q) * G;
+                    const int v = min(nu, hi - 1);
+                    const int key2 = keyL[v];
+                    const int kn = KY::k(key2), ln = KY::l(key2);
+                    const double2 cbn = cbL[v];
+                    const double h = (q0 + q < NQ && nu < hi && nu > mu) ? hW : 0.0;
+                    sr[q] = h * cbn.x;                  // sbar / 2
+                    si[q] = h * cbn.y;
+                    int oa, ob, oc, od;
+                    zo.get(kn, ln, oa, ob, oc, od);
+                    za[q] = lds_at(buf, oa);
+                    zb[q] = lds_at(buf, ob);
+                    zc[q] = lds_at(buf, oc);
+                    zd[q] = lds_at(buf, od);
                 }
-                {   // -Re(sbar conj(c D[u_nu - u_mu]))
-                    const double qr = c.x * Dd.x - c.y * Dd.y, qi = c.x * Dd.y + c.y * Dd.x;
-                    rr -= sr * qr + si * qi;
-                }
-                if (pr) {
-                    double2 Ws, Ds;
-                    wd_at<T>(buf, kn + ku, ln + lu, Ws, Ds);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // 2 W and 2 D (D = DFT(dw/drho)) at u_nu - u_mu and u_nu + u_mu
+                    const double wdr = za[q].x + zb[q].x, wdi = za[q].y - zb[q].y;
+                    const double ddr = za[q].y + zb[q].y, ddi = zb[q].x - za[q].x;
                     if (cross) {
-                        ar -= sr * Ws.x + si * Ws.y;
-                        ai -= sr * Ws.y - si * Ws.x;
+                        ar -= sr[q] * wdr + si[q] * wdi;
+                        ai -= si[q] * wdr - sr[q] * wdi;
                     }
-                    // -Re(sbar conj(conj(c) D[u_nu + u_mu]))
-                    const double qr = c.x * Ds.x + c.y * Ds.y, qi = c.x * Ds.y - c.y * Ds.x;
-                    rr -= sr * qr + si * qi;
+                    {   // -Re(sbar conj(c D[u_nu - u_mu]))
+                        const double qr = c.x * ddr - c.y * ddi, qi = c.x * ddi + c.y * ddr;
+                        rr -= sr[q] * qr + si[q] * qi;
+                    }
+                    if (pr) {
+                        const double wsr = zc[q].x + zd[q].x, wsi = zc[q].y - zd[q].y;
+                        const double dsr = zc[q].y + zd[q].y, dsi = zd[q].x - zc[q].x;
+                        if (cross) {
+                            ar -= sr[q] * wsr + si[q] * wsi;
+                            ai -= sr[q] * wsi - si[q] * wsr;
+                        }
+                        // -Re(sbar conj(conj(c) D[u_nu + u_mu]))
+                        const double qr = c.x * dsr + c.y * dsi, qi = c.x * dsi - c.y * dsr;
+                        rr -= sr[q] * qr + si[q] * qi;
+                    }
                 }
             }
-            if (cross) {
+            for (int o = 1; o < G; o <<= 1) {
+                ar += __shfl_xor(ar, o, 64);
+                ai += __shfl_xor(ai, o, 64);
+            }
+            if (cross && g == 0) {
                 const double2 o = cbL[mu];
                 cbL[mu] = make_double2(o.x + ar, o.y + ai);
             }
@@ -289,23 +395,17 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     for (int i = tid; i < T * T; i += NT) buf[i] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int nu = tid; nu < K; nu += NT) {
-        const int key = keyL[nu];
-        const int kk = zi<T>(KY::k(key), KY::l(key));
-        bool first = true;
-        for (int j = 0; j < nu; ++j)
-            if (zi<T>(KY::k(keyL[j]), KY::l(keyL[j])) == kk) {
-                first = false;
-                break;
-            }
-        if (first) {
-            double sr = 0.0, si = 0.0;
-            for (int j = nu; j < K; ++j)
-                if (zi<T>(KY::k(keyL[j]), KY::l(keyL[j])) == kk) {
-                    sr += cbL[j].x;
-                    si += cbL[j].y;
-                }
-            buf[kk] = make_double2(gW * sr, -gW * si);
+        const int kk = keyL[nu];
+        int first = K;
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < K; ++j) {       // same trip count everywhere: broadcast reads
+            const bool m = keyL[j] == kk;
+            const double2 cbj = cbL[j];
+            first = m && j < first ? j : first;
+            sr += m ? cbj.x : 0.0;
+            si += m ? cbj.y : 0.0;
         }
+        if (first == nu) buf[kk] = make_double2(gW * sr, -gW * si);
     }
     __syncthreads();
     fft_stage_a<T, NT>(buf, tw, T, T, 1, tid);
@@ -318,17 +418,37 @@ __global__ __launch_bounds__(256, 2) void fofse_bwd_kernel(BParams p) {
     __syncthreads();
 
     // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f)
-    for (int i = tid; i < MN; i += NT) {
-        const int m = i / N, n = i - m * N;
-        bool a = p.target[i] == 0;
-        if (p.known) a = a && p.known[ab + i] != 0;
-        double gv = 0.0;
-        if (a) {
-            const double wfb = buf[FftPlan<T>::perm(m) * T + FftPlan<T>::perm(n)].x;
-            gv = p.wtab[i] * wfb;
-            racc += p.dwtab[i] * (double)p.areas[ab + i] * wfb;
+    {
+        bool a[PPT];
+        float fv[PPT];
+        double w[PPT], dw[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int i = tid + j * NT;
+            a[j] = false;
+            fv[j] = 0.0f;
+            w[j] = dw[j] = 0.0;
+            if (i < MN) {
+                a[j] = p.target[i] == 0 && (!p.known || p.known[ab + i] != 0);
+                fv[j] = p.areas[ab + i];
+                w[j] = p.wtab[i];
+                dw[j] = p.dwtab[i];
+            }
         }
-        if (p.grad_areas) p.grad_areas[ab + i] = (float)gv;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int i = tid + j * NT;
+            if (i < MN) {
+                const int m = i / N, n = i - m * N;
+                double gv = 0.0;
+                if (a[j]) {
+                    const double wfb = buf[FftPlan<T>::perm(m) * T + FftPlan<T>::perm(n)].x;
+                    gv = w[j] * wfb;
+                    racc += dw[j] * (double)fv[j] * wfb;
+                }
+                if (p.grad_areas) p.grad_areas[ab + i] = (float)gv;
+            }
+        }
     }
 
     racc = wave_sum(racc);
