@@ -32,6 +32,32 @@ FP64_VECTOR_PEAK = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
 
 
+# HBM traffic of the main forward kernel per launch on the 16-frame batch,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
+# of ``bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame
+# --copy-calibration 256``.  In those runs a plain 256 MiB device copy read
+# FETCH_SIZE = 131,089 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is scaled
+# by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel sources it
+# was taken on (hash below); otherwise the bench reports null.
+KERNEL_SOURCES = ("fofse_group.hip", "iterate.hpp", "device_common.hpp", "fofse_kernel.h")
+TRAFFIC = {"sources_sha256_16": "f5371304433aa6eb", "blocks": 12864,
+           "fetch_kib": 84137.5, "write_kib": 64393.3, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def measured_traffic(n_blocks: int):
+    """HBM bytes per launch of the main forward kernel, or None when the kernel
+    sources or the batch differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2207_01205_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["sources_sha256_16"] or n_blocks != TRAFFIC["blocks"]:
+        return None
+    kib = TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]
+    return kib * 1024.0
+
+
 def flops_per_block(T: int, K: int) -> float:
     """Algorithmic FLOP of one block: per iteration 19 per conjugate class
     (|R|^2: 3, two complex multiply-adds: 16) over T^2/2 + 2 classes, plus two
@@ -302,7 +328,9 @@ def main():
         "single_frame": (None if t_frame is None else
                          {"blocks": n1, "ms": t_frame * 1e3, "blocks_per_s": n1 / t_frame}),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                     "traffic": measured_traffic(n) if kname.startswith("fofse_group") else None,
+                     "traffic_unit": "bytes per launch (HBM, counters scaled by a copy of known size)",
                      "kernel": kname, "flop_per_block": fpb,
                      "avg_launch_ms": kern * 1e3, "avg_step_ms": float(np.mean(per_step)) * 1e3},
         "block_status_nonzero": int(np.count_nonzero(status)),

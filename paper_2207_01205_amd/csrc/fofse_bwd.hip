@@ -252,132 +252,180 @@ __global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BPa
     }
     __syncthreads();
 
-    // transposed recurrence, panels of P iterations from the last
+    // Transposed recurrence in panels of P iterations, from the last panel.
+    // Step pn: wave 0 takes the contributions of the panel solved in the
+    // previous step (pn + 1) into panel pn and then resolves panel pn serially;
+    // at the same time waves 1-3 apply panel pn + 1 to every iteration before
+    // panel pn and accumulate the rho terms of all its pairs.  One barrier per
+    // step; the last step (pn = -1) only finishes the rho terms of panel 0.
     constexpr int P = 16;
     const double hW = 0.5 * gW;         // sbar / 2 absorbs the halving in W = (Z + conj Z(-k)) / 2
     double racc = 0.0;
-    for (int pn = (K - 1) / P; pn >= 0; --pn) {
-        const int base = pn * P, cnt = min(P, K - base), hi = base + cnt;
+    const int NPAN = (K + P - 1) / P;
+    int kprev = 0;                       // wave 0: classes and finished adjoints of panel pn + 1
+    double2 cprev = make_double2(0.0, 0.0);
+    for (int pn = NPAN - 1; pn >= -1; --pn) {
+        const int base = pn >= 0 ? pn * P : 0;
+        const int cnt = pn >= 0 ? min(P, K - base) : 0;
+        const int pbase = (pn + 1) * P;
+        const int pcnt = pn + 1 < NPAN ? min(P, K - pbase) : 0;
+        const int phi = pbase + pcnt;
         if (wave == 0) {
-            // lanes 0..cnt-1 = iterations base..hi-1.  Each lane first takes the
-            // W samples it needs from every later iteration of the panel into
-            // registers; the serial sweep then touches no memory: the finished
-            // adjoint of iteration j reaches the other lanes by readlane.
-            const bool valid = lane < cnt;
-            const int key = valid ? keyL[base + lane] : 0;
-            const int ku = KY::k(key), lu = KY::l(key);
-            const bool pr = KY::pair(ku, lu);
-            double2 cb = valid ? cbL[base + lane] : make_double2(0.0, 0.0);
-            double wr[P], wi[P], vr[P], vi[P];     // 2 W[u_j - u_i], 2 W[u_j + u_i]
-            if (lane < P) {
+            if (pn >= 0) {
+                const bool valid = lane < cnt;
+                const int key = valid ? keyL[base + lane] : 0;
+                const int ku = KY::k(key), lu = KY::l(key);
+                const bool pr = KY::pair(ku, lu);
+                double2 cb = valid ? cbL[base + lane] : make_double2(0.0, 0.0);
                 const ZOff<T> zo(ku, lu);
+                // contributions of panel pn + 1 (lane u of kprev / cprev)
+                if (valid) {
+                    for (int u0 = 0; u0 < pcnt; u0 += 4) {
+                        double sr[4], si[4];
+                        double2 za[4], zb[4], zc[4], zd[4];
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int jj = min(j, cnt - 1);
-                    const int kj = __builtin_amdgcn_readlane(ku, jj), lj = __builtin_amdgcn_readlane(lu, jj);
-                    int oa, ob, oc, od;
-                    zo.get(kj, lj, oa, ob, oc, od);
-                    const double2 za = lds_at(buf, oa), zb = lds_at(buf, ob);
-                    const double2 zc = lds_at(buf, oc), zd = lds_at(buf, od);
-                    wr[j] = za.x + zb.x;
-                    wi[j] = za.y - zb.y;
-                    vr[j] = zc.x + zd.x;
-                    vi[j] = zc.y - zd.y;
-                }
-            }
+                        for (int q = 0; q < 4; ++q) {
+                            const int u = min(u0 + q, pcnt - 1);
+                            const int kn = __builtin_amdgcn_readlane(kprev, u);
+                            const double h = u0 + q < pcnt ? hW : 0.0;
+                            sr[q] = h * readlane_f64(cprev.x, u);
+                            si[q] = h * readlane_f64(cprev.y, u);
+                            int oa, ob, oc, od;
+                            zo.get(KY::k(kn), KY::l(kn), oa, ob, oc, od);
+                            za[q] = lds_at(buf, oa);
+                            zb[q] = lds_at(buf, ob);
+                            zc[q] = lds_at(buf, oc);
+                            zd[q] = lds_at(buf, od);
+                        }
 #pragma unroll
-            for (int j = P - 1; j >= 0; --j) {
-                if (j < cnt) {
-                    const int keyj = __builtin_amdgcn_readlane(key, j);
-                    const bool pj = KY::pair(KY::k(keyj), KY::l(keyj));
-                    const double cr = readlane_f64(cb.x, j);
-                    const double ci = pj ? readlane_f64(cb.y, j) : 0.0;
-                    if (lane == j) cb = make_double2(cr, ci);      // final adjoint of c_j
-                    const double sr = hW * cr, si = hW * ci;       // sbar_j / 2
-                    if (lane < j) {
-                        cb.x -= sr * wr[j] + si * wi[j];            // sbar conj(W[u_j - u_i])
-                        cb.y -= si * wr[j] - sr * wi[j];
-                        if (pr) {
-                            cb.x -= sr * vr[j] + si * vi[j];        // conj(sbar) W[u_j + u_i]
-                            cb.y -= sr * vi[j] - si * vr[j];
+                        for (int q = 0; q < 4; ++q) {
+                            const double wdr = za[q].x + zb[q].x, wdi = za[q].y - zb[q].y;
+                            cb.x -= sr[q] * wdr + si[q] * wdi;
+                            cb.y -= si[q] * wdr - sr[q] * wdi;
+                            if (pr) {
+                                const double wsr = zc[q].x + zd[q].x, wsi = zc[q].y - zd[q].y;
+                                cb.x -= sr[q] * wsr + si[q] * wsi;
+                                cb.y -= sr[q] * wsi - si[q] * wsr;
+                            }
                         }
                     }
                 }
-            }
-            if (valid) cbL[base + lane] = cb;
-        }
-        __syncthreads();
-        // The panel's sbar into the earlier iterations (mu < base), and the
-        // rho terms of every pair mu < nu with nu in the panel.  G threads
-        // (adjacent lanes) share the panel's iterations of one mu, so that
-        // about hi * P pairs spread over the workgroup; their partial sums
-        // meet by butterfly shuffles (fixed order).
-        const int G = hi <= 16 ? 16 : hi <= 32 ? 8 : hi <= 64 ? 4 : hi <= 128 ? 2 : 1;
-        const int NQ = P / G;
-        for (int t = tid; t < hi * G; t += NT) {
-            const int mu = t / G, g = t - mu * G;
-            const int key = keyL[mu];
-            const int ku = KY::k(key), lu = KY::l(key);
-            const bool pr = KY::pair(ku, lu);
-            const bool cross = mu < base;
-            const double2 c = cL[mu];
-            const ZOff<T> zo(ku, lu);
-            double ar = 0.0, ai = 0.0, rr = 0.0;
-            for (int q0 = 0; q0 < NQ; q0 += 4) {
-                double sr[4], si[4];
-                double2 za[4], zb[4], zc[4], zd[4];
+                // serial sweep of panel pn.  Each lane first takes the W samples
+                // it needs from every later iteration of the panel into
+                // registers; the sweep then touches no memory: the finished
+                // adjoint of iteration j reaches the other lanes by readlane.
+                double wr[P], wi[P], vr[P], vi[P];     // 2 W[u_j - u_i], 2 W[u_j + u_i]
+                if (lane < P) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int nu = base + g + (q0 + q) * G;
-                    const int v = min(nu, hi - 1);
-                    const int key2 = keyL[v];
-                    const int kn = KY::k(key2), ln = KY::l(key2);
-                    const double2 cbn = cbL[v];
-                    const double h = (q0 + q < NQ && nu < hi && nu > mu) ? hW : 0.0;
-                    sr[q] = h * cbn.x;                  // sbar / 2
-                    si[q] = h * cbn.y;
-                    int oa, ob, oc, od;
-                    zo.get(kn, ln, oa, ob, oc, od);
-                    za[q] = lds_at(buf, oa);
-                    zb[q] = lds_at(buf, ob);
-                    zc[q] = lds_at(buf, oc);
-                    zd[q] = lds_at(buf, od);
+                    for (int j = 0; j < P; ++j) {
+                        const int jj = min(j, cnt - 1);
+                        const int kj = __builtin_amdgcn_readlane(ku, jj), lj = __builtin_amdgcn_readlane(lu, jj);
+                        int oa, ob, oc, od;
+                        zo.get(kj, lj, oa, ob, oc, od);
+                        const double2 za = lds_at(buf, oa), zb = lds_at(buf, ob);
+                        const double2 zc = lds_at(buf, oc), zd = lds_at(buf, od);
+                        wr[j] = za.x + zb.x;
+                        wi[j] = za.y - zb.y;
+                        vr[j] = zc.x + zd.x;
+                        vi[j] = zc.y - zd.y;
+                    }
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    // 2 W and 2 D (D = DFT(dw/drho)) at u_nu - u_mu and u_nu + u_mu
-                    const double wdr = za[q].x + zb[q].x, wdi = za[q].y - zb[q].y;
-                    const double ddr = za[q].y + zb[q].y, ddi = zb[q].x - za[q].x;
-                    if (cross) {
-                        ar -= sr[q] * wdr + si[q] * wdi;
-                        ai -= si[q] * wdr - sr[q] * wdi;
+                for (int j = P - 1; j >= 0; --j) {
+                    if (j < cnt) {
+                        const int keyj = __builtin_amdgcn_readlane(key, j);
+                        const bool pj = KY::pair(KY::k(keyj), KY::l(keyj));
+                        const double cr = readlane_f64(cb.x, j);
+                        const double ci = pj ? readlane_f64(cb.y, j) : 0.0;
+                        if (lane == j) cb = make_double2(cr, ci);  // final adjoint of c_j
+                        const double sr = hW * cr, si = hW * ci;   // sbar_j / 2
+                        if (lane < j) {
+                            cb.x -= sr * wr[j] + si * wi[j];        // sbar conj(W[u_j - u_i])
+                            cb.y -= si * wr[j] - sr * wi[j];
+                            if (pr) {
+                                cb.x -= sr * vr[j] + si * vi[j];    // conj(sbar) W[u_j + u_i]
+                                cb.y -= sr * vi[j] - si * vr[j];
+                            }
+                        }
                     }
-                    {   // -Re(sbar conj(c D[u_nu - u_mu]))
-                        const double qr = c.x * ddr - c.y * ddi, qi = c.x * ddi + c.y * ddr;
-                        rr -= sr[q] * qr + si[q] * qi;
+                }
+                if (valid) cbL[base + lane] = cb;
+                kprev = key;
+                cprev = cb;
+            }
+        } else if (pcnt > 0) {
+            // Waves 1-3: panel pn + 1 into the iterations mu < base, and the rho
+            // terms of every pair mu < nu with nu in panel pn + 1.  G threads
+            // (adjacent lanes) share the panel's iterations of one mu; their
+            // partial sums meet by butterfly shuffles (fixed order).
+            constexpr int NT3 = NT - 64;
+            const int G = phi * 16 <= NT3 ? 16 : phi * 8 <= NT3 ? 8 : phi * 4 <= NT3 ? 4 : phi * 2 <= NT3 ? 2 : 1;
+            const int NQ = P / G;
+            for (int t = tid - 64; t < phi * G; t += NT3) {
+                const int mu = t / G, g = t - mu * G;
+                const int key = keyL[mu];
+                const int ku = KY::k(key), lu = KY::l(key);
+                const bool pr = KY::pair(ku, lu);
+                const bool cross = mu < base && pn >= 0;
+                const double2 c = cL[mu];
+                const ZOff<T> zo(ku, lu);
+                double ar = 0.0, ai = 0.0, rr = 0.0;
+                for (int q0 = 0; q0 < NQ; q0 += 4) {
+                    double sr[4], si[4];
+                    double2 za[4], zb[4], zc[4], zd[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int nu = pbase + g + (q0 + q) * G;
+                        const int v = min(nu, phi - 1);
+                        const int key2 = keyL[v];
+                        const int kn = KY::k(key2), ln = KY::l(key2);
+                        const double2 cbn = cbL[v];
+                        const double h = (q0 + q < NQ && nu < phi && nu > mu) ? hW : 0.0;
+                        sr[q] = h * cbn.x;              // sbar / 2
+                        si[q] = h * cbn.y;
+                        int oa, ob, oc, od;
+                        zo.get(kn, ln, oa, ob, oc, od);
+                        za[q] = lds_at(buf, oa);
+                        zb[q] = lds_at(buf, ob);
+                        zc[q] = lds_at(buf, oc);
+                        zd[q] = lds_at(buf, od);
                     }
-                    if (pr) {
-                        const double wsr = zc[q].x + zd[q].x, wsi = zc[q].y - zd[q].y;
-                        const double dsr = zc[q].y + zd[q].y, dsi = zd[q].x - zc[q].x;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // 2 W and 2 D (D = DFT(dw/drho)) at u_nu - u_mu and u_nu + u_mu
+                        const double wdr = za[q].x + zb[q].x, wdi = za[q].y - zb[q].y;
+                        const double ddr = za[q].y + zb[q].y, ddi = zb[q].x - za[q].x;
                         if (cross) {
-                            ar -= sr[q] * wsr + si[q] * wsi;
-                            ai -= sr[q] * wsi - si[q] * wsr;
+                            ar -= sr[q] * wdr + si[q] * wdi;
+                            ai -= si[q] * wdr - sr[q] * wdi;
                         }
-                        // -Re(sbar conj(conj(c) D[u_nu + u_mu]))
-                        const double qr = c.x * dsr + c.y * dsi, qi = c.x * dsi - c.y * dsr;
-                        rr -= sr[q] * qr + si[q] * qi;
+                        {   // -Re(sbar conj(c D[u_nu - u_mu]))
+                            const double qr = c.x * ddr - c.y * ddi, qi = c.x * ddi + c.y * ddr;
+                            rr -= sr[q] * qr + si[q] * qi;
+                        }
+                        if (pr) {
+                            const double wsr = zc[q].x + zd[q].x, wsi = zc[q].y - zd[q].y;
+                            const double dsr = zc[q].y + zd[q].y, dsi = zd[q].x - zc[q].x;
+                            if (cross) {
+                                ar -= sr[q] * wsr + si[q] * wsi;
+                                ai -= sr[q] * wsi - si[q] * wsr;
+                            }
+                            // -Re(sbar conj(conj(c) D[u_nu + u_mu]))
+                            const double qr = c.x * dsr + c.y * dsi, qi = c.x * dsi - c.y * dsr;
+                            rr -= sr[q] * qr + si[q] * qi;
+                        }
                     }
                 }
+                for (int o = 1; o < G; o <<= 1) {
+                    ar += __shfl_xor(ar, o, 64);
+                    ai += __shfl_xor(ai, o, 64);
+                }
+                if (cross && g == 0) {
+                    const double2 o = cbL[mu];
+                    cbL[mu] = make_double2(o.x + ar, o.y + ai);
+                }
+                racc += rr;
             }
-            for (int o = 1; o < G; o <<= 1) {
-                ar += __shfl_xor(ar, o, 64);
-                ai += __shfl_xor(ai, o, 64);
-            }
-            if (cross && g == 0) {
-                const double2 o = cbL[mu];
-                cbL[mu] = make_double2(o.x + ar, o.y + ai);
-            }
-            racc += rr;
         }
         __syncthreads();
     }
