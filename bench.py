@@ -81,6 +81,23 @@ def _frame(i):
     return a.areas, a.known, a.target, a.truth
 
 
+def _frame4k(i):
+    from paper_2207_01205_amd import synth
+    a = synth.frame_concealment(i, 5000 + i, height=2160, width=3840, fraction=0.05)
+    return a.areas, a.known, a.target, a.truth
+
+
+def make_tuning_workload(n_train: int, n_held: int):
+    """3840 x 2160 frames with 5 % of the 16 x 16 blocks lost (1,620 per
+    frame): n_train frames for the fit, n_held further frames for the PSNR."""
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        parts = pool.map(_frame4k, range(n_train + n_held))
+    cat = lambda j, sl: np.concatenate([p[j] for p in parts[sl]])
+    tr = slice(0, n_train)
+    he = slice(n_train, n_train + n_held)
+    return ((cat(0, tr), cat(1, tr), cat(3, tr)), (cat(0, he), cat(1, he), cat(3, he)), parts[0][2])
+
+
 def make_workload(n_frames: int):
     with mp.get_context("fork").Pool(min(16, n_frames, os.cpu_count() or 1)) as pool:
         parts = pool.map(_frame, range(n_frames))
@@ -149,6 +166,88 @@ def _cpu_model():
     return None
 
 
+def run_tuning(data, args, dev):
+    """Adam on theta with (rho_hat, gamma) = sigmoid(theta), loss = MSE on B
+    against the true pixels over every lost block of the training frames; the
+    gradient comes from one replay of the captured forward+adjoint graph."""
+    import torch
+    from paper_2207_01205_amd import fofse as F
+    (tr_a, tr_k, tr_t), (he_a, he_k, he_t), target = data
+    tb = target.reshape(-1) == 1
+    plan = F.Plan(AREA, AREA, T, K, target, device=0)
+    nB = plan.nB
+
+    def put(a, k, t):
+        n = len(a)
+        return (n, torch.from_numpy(a).to(dev), torch.from_numpy(k).to(dev),
+                torch.from_numpy(np.ascontiguousarray(t.reshape(n, -1)[:, tb])).to(dev))
+
+    n, a, k, truth = put(tr_a, tr_k, tr_t)
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    out = torch.empty((n, nB), dtype=torch.float32, device=dev)
+    sel = torch.empty((n, K), dtype=torch.int32, device=dev)
+    coef = torch.empty((n, K, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    gout = torch.empty_like(out)
+    grg = torch.empty((2,), dtype=torch.float64, device=dev)
+    gblk = torch.empty((n, 2), dtype=torch.float64, device=dev)
+
+    def step():
+        s = torch.cuda.current_stream(dev).cuda_stream
+        F.fofse_extrapolate_batch(plan.handle, n, a.data_ptr(), k.data_ptr(), rg.data_ptr(),
+                                  out.data_ptr(), sel.data_ptr(), coef.data_ptr(), st.data_ptr(), s)
+        torch.sub(out, truth, out=gout)
+        gout.mul_(2.0 / gout.numel())
+        F.fofse_backward(plan.handle, n, a.data_ptr(), k.data_ptr(), rg.data_ptr(), sel.data_ptr(),
+                         coef.data_ptr(), gout.data_ptr(), 0, grg.data_ptr(), gblk.data_ptr(), s)
+
+    def heldout_psnr(params):
+        nh, ha, hk, ht = put(he_a, he_k, he_t)
+        p = torch.tensor(params, dtype=torch.float64, device=dev)
+        o, _, _, _ = plan.extrapolate(ha, p, known=hk)
+        mse = ((o.clamp(0.0, 255.0) - ht) ** 2).mean().item()
+        return 10.0 * np.log10(255.0 ** 2 / mse)
+
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    theta = torch.logit(torch.tensor([RHO, GAMMA], dtype=torch.float64)).requires_grad_(True)
+    opt = torch.optim.Adam([theta], lr=args.tune_lr)
+    psnr0 = heldout_psnr([RHO, GAMMA])
+    losses, t_steps = [], 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for it in range(args.tune):
+        params = torch.sigmoid(theta.detach())
+        rg.copy_(params)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        t_steps += e0.elapsed_time(e1) * 1e-3
+        losses.append(((out - truth) ** 2).mean().item())
+        g = grg.cpu()
+        theta.grad = g * params * (1.0 - params)
+        opt.step()
+        print(f"[tune] step {it}: rho {params[0].item():.4f} gamma {params[1].item():.4f} "
+              f"loss {losses[-1]:.4f}", file=sys.stderr, flush=True)
+    final = [float(x) for x in torch.sigmoid(theta.detach())]
+    psnr1 = heldout_psnr(final)
+    del graph
+    return {"frames": args.tune_frames, "frame": "3840x2160", "loss_fraction": 0.05,
+            "blocks_per_step": n, "steps": args.tune, "optimizer": f"Adam lr {args.tune_lr} on logit",
+            "blocks_per_s": n * args.tune / t_steps, "ms_per_step": t_steps / args.tune * 1e3,
+            "rho_gamma_start": [RHO, GAMMA], "rho_gamma_end": final,
+            "loss_start": losses[0], "loss_end": losses[-1],
+            "heldout_psnr_db_start": psnr0, "heldout_psnr_db_end": psnr1,
+            "heldout": "8 further frames, PSNR over the lost-block pixels, output clipped to 0..255"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +257,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
+                    help="also fit (rho_hat, gamma) by Adam for STEPS steps on 64 synthetic "
+                         "3840x2160 frames with 5%% block loss, one captured graph per step "
+                         "(forward, MSE gradient, adjoint), and report held-out PSNR")
+    ap.add_argument("--tune-frames", type=int, default=64)
+    ap.add_argument("--tune-lr", type=float, default=0.1)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, copy MIB MiB once with a plain device copy, so "
                          "that a counter run can scale FETCH_SIZE / WRITE_SIZE by known bytes")
@@ -174,6 +279,7 @@ def main():
 
     # everything that forks runs before the GPU is initialised
     areas, known, target, truth = make_workload(args.frames)
+    tune_data = make_tuning_workload(args.tune_frames, 8) if args.tune > 0 else None
     n = len(areas)
     base = None
     if not args.no_cpu_baseline:
@@ -259,13 +365,19 @@ def main():
         grg = torch.empty((2,), dtype=torch.float64, device=dev)
         gblk = torch.empty((n, 2), dtype=torch.float64, device=dev)
 
-        def step_adj():
-            step()
+        def step_adj(s=None):
+            s = stream.cuda_stream if s is None else s
+            F.fofse_extrapolate_batch(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(),
+                                      rg.data_ptr(), out.data_ptr(), sel.data_ptr(),
+                                      coef.data_ptr(), st.data_ptr(), s)
             torch.sub(out, d_truth, out=gout)
             gout.mul_(2.0 / gout.numel())
             F.fofse_backward(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(), rg.data_ptr(),
                              sel.data_ptr(), coef.data_ptr(), gout.data_ptr(), gareas.data_ptr(),
-                             grg.data_ptr(), gblk.data_ptr(), stream.cuda_stream)
+                             grg.data_ptr(), gblk.data_ptr(), s)
+
+        def step_graphable():
+            step_adj(torch.cuda.current_stream(dev).cuda_stream)
 
         for _ in range(args.warmup):
             step_adj()
@@ -294,6 +406,33 @@ def main():
                "grad_rho_gamma": [float(x) for x in grg.cpu().numpy()]}
         print(f"[bench] fwd+adjoint: {t_adj / args.steps * 1e3:.3f} ms per step, adjoint kernel "
               f"{bwd_k * 1e3:.3f} ms", file=sys.stderr, flush=True)
+
+    # the same forward+adjoint step captured in one HIP graph and replayed
+    if adj is not None:
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step_graphable()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step_graphable()
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        eg = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        eg[0].record(stream)
+        for _ in range(args.steps):
+            graph.replay()
+        eg[1].record(stream)
+        torch.cuda.synchronize()
+        t_g = eg[0].elapsed_time(eg[1]) * 1e-3
+        adj["graph_value"] = n * args.steps / t_g
+        adj["graph_ms_per_step"] = t_g / args.steps * 1e3
+        del graph
+
+    tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
 
     # final full-batch pass for the outputs checked below
     step()
@@ -336,6 +475,8 @@ def main():
         "block_status_nonzero": int(np.count_nonzero(status)),
         "fwd_adjoint": adj,
     }
+    if tuning is not None:
+        result["tuning"] = tuning
     if base is not None:
         info, ref = base
         info["sample_parity"] = sample_parity(ref, out_h, sel_h)
