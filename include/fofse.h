@@ -51,7 +51,7 @@ typedef enum {
  *   area_h, area_w : M, N, the area size (1 <= M, N <= fft_size).  The isotropic
  *                    model is centred at ((M-1)/2, (N-1)/2) (eq. 15).
  *   fft_size       : T, the DFT size (the paper's FFT size, Section 3).
- *                    Supported: 32 and 64.
+ *                    Supported: 16, 32 and 64.
  *   iterations     : K >= 0, the number of iterations (the paper's I, Table 1),
  *                    at most 4096.
  *   target_mask    : host, M*N bytes row-major, non-zero on the missing area B.

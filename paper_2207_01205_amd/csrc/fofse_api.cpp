@@ -46,7 +46,7 @@ namespace {
 // block) finishes sooner than the grouped path (one wave per block).
 constexpr int kGroupedMinBlocksPerCu = 8;
 
-bool fft_size_built(int T) { return T == 32 || T == 64; }
+bool fft_size_built(int T) { return T == 16 || T == 32 || T == 64; }
 
 // Keeps the caller's current device across a library call.
 struct DeviceGuard {

@@ -55,7 +55,7 @@ __device__ __forceinline__ int zp(int k, int l) {
 
 template <int T>
 struct Key {
-    static constexpr int LOG2 = T == 64 ? 6 : 5;
+    static constexpr int LOG2 = T == 128 ? 7 : T == 64 ? 6 : T == 32 ? 5 : 4;
     __device__ static int k(int key) { return (key >> LOG2) & (T - 1); }
     __device__ static int l(int key) { return key & (T - 1); }
     __device__ static bool pair(int k, int l) {
@@ -552,12 +552,13 @@ static hipError_t launch_bwd(const BParams& p, hipStream_t stream) {
 
 hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
                            const Timing& tm) {
-    if ((p.T != 64 && p.T != 32) || p.K > kBackwardMaxK) return hipErrorInvalidValue;
+    if ((p.T != 64 && p.T != 32 && p.T != 16) || p.K > kBackwardMaxK) return hipErrorInvalidValue;
     hipError_t e = launch_weights(wp, stream);
     if (e != hipSuccess) return e;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
     if (p.T == 64) e = p.K <= 256 ? launch_bwd<64, 256>(p, stream) : launch_bwd<64, kBackwardMaxK>(p, stream);
-    else e = p.K <= 256 ? launch_bwd<32, 256>(p, stream) : launch_bwd<32, kBackwardMaxK>(p, stream);
+    else if (p.T == 32) e = p.K <= 256 ? launch_bwd<32, 256>(p, stream) : launch_bwd<32, kBackwardMaxK>(p, stream);
+    else e = p.K <= 256 ? launch_bwd<16, 256>(p, stream) : launch_bwd<16, kBackwardMaxK>(p, stream);
     if (e != hipSuccess) return e;
     if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
     if (d_sum) {

@@ -11,6 +11,7 @@ namespace fofse {
 // Waves per workgroup (one workgroup = one block) for each FFT size.
 constexpr int kWaves64 = 4;
 constexpr int kWaves32 = 2;
+constexpr int kWaves16 = 1;
 
 struct KParams {
     int n_blocks;

@@ -257,3 +257,39 @@ def random_tiny(seed: int, m: int, n: int, p_known: float = 0.7):
         known[0, 0] = 1
     target = (1 - known).astype(np.uint8)
     return f, known, target
+
+
+# block (lost B side), support width, FFT size, iterations of the four classes
+# of the mixed-size workload: 4x4 / 8x8 / 16x16 / 32x32 losses
+MIXED_CLASSES = ((4, 4, 16, 32), (8, 8, 32, 64), (16, 16, 64, 200), (32, 16, 128, 300))
+
+
+def mixed_blocks(frame_img: np.ndarray, pos_seed: int, block: int, support: int, n: int):
+    """n lost blocks of size ``block`` at seeded positions of the frame's block
+    grid, each with an area of side block + 2 * support lying fully inside the
+    frame (so every area has the complement of B as support).
+
+    Returns (areas float32 (n, A, A), target uint8 (A, A), truth float32 (n, A, A),
+    origin int64 (n, 2)); areas hold the frame pixels with B zeroed."""
+    height, width = frame_img.shape
+    side = block + 2 * support
+    rng = np.random.default_rng(pos_seed)
+    # block-grid cells whose area stays inside the frame
+    r_lo = -(-support // block)
+    r_hi = (height - block - support) // block
+    c_lo = r_lo
+    c_hi = (width - block - support) // block
+    rows = rng.integers(r_lo, r_hi + 1, n)
+    cols = rng.integers(c_lo, c_hi + 1, n)
+    target = np.zeros((side, side), np.uint8)
+    target[support:support + block, support:support + block] = 1
+    areas = np.zeros((n, side, side), np.float32)
+    truth = np.zeros((n, side, side), np.float32)
+    origin = np.zeros((n, 2), np.int64)
+    for i, (r, c) in enumerate(zip(rows, cols)):
+        y0, x0 = block * r - support, block * c - support
+        origin[i] = (y0, x0)
+        sub = frame_img[y0:y0 + side, x0:x0 + side].astype(np.float32)
+        truth[i] = sub
+        areas[i] = np.where(target == 1, 0.0, sub)
+    return areas, target, truth, origin
