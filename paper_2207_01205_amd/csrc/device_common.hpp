@@ -54,11 +54,36 @@ __device__ __forceinline__ void dft8(double2* x) {
     x[7] = c_sub(e[3], t3);
 }
 
+// length 16 as two length-8 DFTs (even and odd samples) and twiddles
+// exp(-j 2 pi k / 16)
+__device__ __forceinline__ void dft16(double2* x) {
+    double2 e[8], o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        e[i] = x[2 * i];
+        o[i] = x[2 * i + 1];
+    }
+    dft8(e);
+    dft8(o);
+    const double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;   // cos, sin(pi/8)
+    const double r = 0.70710678118654752440;
+    const double2 w[8] = {make_double2(1.0, 0.0), make_double2(c1, -s1), make_double2(r, -r),
+                          make_double2(s1, -c1), make_double2(0.0, -1.0), make_double2(-s1, -c1),
+                          make_double2(-r, -r), make_double2(-c1, -s1)};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double2 t = k ? c_mul(o[k], w[k]) : o[k];
+        x[k] = c_add(e[k], t);
+        x[k + 8] = c_sub(e[k], t);
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void dft(double2* x) {
     if constexpr (R == 2) dft2(x);
     else if constexpr (R == 4) dft4(x);
-    else dft8(x);
+    else if constexpr (R == 8) dft8(x);
+    else dft16(x);
 }
 
 // ---------------------------------------------------------------------------

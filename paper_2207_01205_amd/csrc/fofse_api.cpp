@@ -46,7 +46,10 @@ namespace {
 // block) finishes sooner than the grouped path (one wave per block).
 constexpr int kGroupedMinBlocksPerCu = 8;
 
-bool fft_size_built(int T) { return T == 16 || T == 32 || T == 64; }
+bool fft_size_built(int T) { return T == 16 || T == 32 || T == 64 || T == 128; }
+
+// The 128-point kernel keeps a 64 x 64 staging tile of the area.
+bool geometry_built(int M, int N, int T) { return fft_size_built(T) && (T != 128 || (M <= 64 && N <= 64)); }
 
 // Keeps the caller's current device across a library call.
 struct DeviceGuard {
@@ -163,7 +166,7 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess) return FOFSE_ERR_DEVICE;
     if (device < 0 || device >= ndev) return FOFSE_ERR_ARG;
-    if (!fft_size_built(T)) return FOFSE_ERR_UNSUPPORTED;
+    if (!geometry_built(M, N, T)) return FOFSE_ERR_UNSUPPORTED;
 
     std::vector<int32_t> bpix;
     for (int i = 0; i < M * N; ++i)
@@ -321,7 +324,7 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
     if (n_blocks == 0) return FOFSE_OK;
     if (!d_areas || !d_rho_gamma || !d_sel || !d_coef || !d_grad_out) return FOFSE_ERR_ARG;
-    if (p->K > fofse::kBackwardMaxK) return FOFSE_ERR_UNSUPPORTED;
+    if (p->K > fofse::kBackwardMaxK || p->T > 64) return FOFSE_ERR_UNSUPPORTED;
     DeviceGuard guard(p->device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;
     double* blk = d_grad_block;

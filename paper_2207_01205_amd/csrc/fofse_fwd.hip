@@ -207,11 +207,12 @@ hipError_t launch_weights(const KParams& p, hipStream_t stream) {
 }
 
 hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm) {
-    if (p.T != 64 && p.T != 32 && p.T != 16) return hipErrorInvalidValue;
+    if (p.T != 128 && p.T != 64 && p.T != 32 && p.T != 16) return hipErrorInvalidValue;
     hipError_t e = launch_weights(p, stream);
     if (e != hipSuccess) return e;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
-    if (p.T == 64) e = launch_fwd<64, kWaves64>(p, stream);
+    if (p.T == 128) e = launch_fwd128(p, stream);
+    else if (p.T == 64) e = launch_fwd<64, kWaves64>(p, stream);
     else if (p.T == 32) e = launch_fwd<32, kWaves32>(p, stream);
     else e = launch_fwd<16, kWaves16>(p, stream);
     if (e != hipSuccess) return e;
@@ -223,6 +224,7 @@ hipError_t launch_synthesis(const KParams& p, hipStream_t stream) {
     if (p.T == 64) hipLaunchKernelGGL(k_synthesize<64>, dim3(p.n_blocks), dim3(256), 0, stream, p);
     else if (p.T == 32) hipLaunchKernelGGL(k_synthesize<32>, dim3(p.n_blocks), dim3(256), 0, stream, p);
     else if (p.T == 16) hipLaunchKernelGGL(k_synthesize<16>, dim3(p.n_blocks), dim3(256), 0, stream, p);
+    else if (p.T == 128) hipLaunchKernelGGL(k_synthesize<128>, dim3(p.n_blocks), dim3(256), 0, stream, p);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

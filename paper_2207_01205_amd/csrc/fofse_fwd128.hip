@@ -1,0 +1,299 @@
+// FOFSE forward kernel for the 128 x 128 DFT (areas up to 64 x 64), gfx950.
+//
+// The iteration is that of the other kernels (Section 2: eq. 9 selection, eqs.
+// 5 and 14 coefficient, eq. 3 carried to the DFT domain); what differs is the
+// storage, because a 128 x 128 spectrum in FP64 (256 KB) exceeds the LDS:
+//
+//   * Placement: area row m -> grid column (index k), area column n -> grid row
+//     (index l), as in the other kernels, so the representative half of the
+//     conjugate classes is grid rows l = 0..64.
+//   * Initial transforms (eqs. 7, 8): for x = w f (then x = w), a direct DFT
+//     over n evaluated only for l = 0..64 (the real input makes the other rows
+//     redundant), then 128-point FFTs over m for each of those 65 rows.  The
+//     result, the row half of the spectrum, occupies 65 x 128 x 16 B = 133 KB.
+//   * R (rows 0..64) lives in registers: 8 wavefronts share the rows, every
+//     lane holds columns lane and lane + 64.
+//   * W stays in LDS as its row half.  A read W[r][c] with r outside 0..64 is
+//     conj(W[-r][-c]) (w is real); for every register slot the choice between
+//     the direct and the mirrored read is uniform (it depends on the slot's row
+//     and the selected u only), and the conjugation is folded into the signs of
+//     the coefficient.
+//   * Columns are stored in the FFT's output order; each lane maps its four
+//     column indices once per iteration.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fofse_kernel.h"
+#include "device_common.hpp"
+#include "iterate.hpp"
+
+namespace fofse {
+
+namespace {
+
+constexpr int T128 = 128;
+constexpr int H128 = 64;
+constexpr int NW128 = 8;
+constexpr int NT128 = NW128 * 64;
+constexpr int ROWS128 = H128 + 1;
+
+__host__ __device__ constexpr int row_begin128(int w) { return (w * ROWS128 + NW128 - 1) / NW128; }
+constexpr int SMAX128 = row_begin128(1) - row_begin128(0);
+
+__device__ __forceinline__ int perm128(int k) { return FftPlan<T128>::perm(k & (T128 - 1)); }
+
+__device__ __forceinline__ double neg_if(bool c, double x) { return c ? -x : x; }
+
+struct Shared128 {
+    double2 spec[ROWS128 * T128];   // row half of a spectrum (FFT column order)
+    double2 tw[T128];
+    Xchg<NW128> xchg[2];
+    int flags;
+};
+
+// Spectrum rows l = 0..64 of x (area values from ``val``, transposed placement)
+// into sh.spec: direct DFT over n for l <= 64, then 128-point FFTs over m.
+// ``val(i)`` gives the value of area sample i = m * N + n (0 outside A).
+template <class F>
+__device__ __forceinline__ void row_half_spectrum(Shared128& sh, int M, int N, int tid, F val) {
+    double* xs = reinterpret_cast<double*>(sh.spec);      // staging xs[n * 64 + m]
+    for (int i = tid; i < 64 * 64; i += NT128) xs[i] = 0.0;
+    __syncthreads();
+    for (int i = tid; i < M * N; i += NT128) {
+        const int m = i / N, n = i - m * N;
+        xs[n * 64 + m] = val(i);
+    }
+    __syncthreads();
+    // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128), l = lg + 8 j
+    const int m = tid & 63, lg = tid >> 6;
+    double2 acc[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = make_double2(0.0, 0.0);
+    for (int n = 0; n < N; ++n) {
+        const double x = xs[n * 64 + m];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int l = lg + 8 * j;
+            const double2 t = sh.tw[(l * n) & (T128 - 1)];
+            acc[j].x = fma(x, t.x, acc[j].x);
+            acc[j].y = fma(x, t.y, acc[j].y);
+        }
+    }
+    __syncthreads();                                        // staging consumed
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const int l = lg + 8 * j;
+        if (l <= H128) {
+            sh.spec[l * T128 + m] = acc[j];
+            sh.spec[l * T128 + 64 + m] = make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    fft_stage_a<T128, NT128>(sh.spec, sh.tw, ROWS128, T128, 1, tid);
+    __syncthreads();
+    fft_stage_b<T128, NT128>(sh.spec, ROWS128, T128, 1, tid);
+    __syncthreads();
+}
+
+// One wavefront's rows [k0, k0 + S) of the K iterations.
+template <int WI>
+__device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_begin128(WI)>& R0,
+                                            RegSpec<row_begin128(WI + 1) - row_begin128(WI)>& R1,
+                                            Shared128& sh, const KParams& p, int b, int lane,
+                                            double gW0) {
+    constexpr int k0 = row_begin128(WI);
+    constexpr int S = row_begin128(WI + 1) - k0;
+    const int K = p.K;
+    const double2* Wb = sh.spec;
+    int u = 0, v = 0;
+    double cr = 0.0, ci = 0.0;
+    const int c0 = lane, c1 = lane + 64;
+    for (int it = 0; it < K; ++it) {
+        // permuted column indices of the four read forms for both columns
+        const int dA0 = perm128(c0 - v), mA0 = perm128(v - c0), dB0 = perm128(c0 + v), mB0 = perm128(-c0 - v);
+        const int dA1 = perm128(c1 - v), mA1 = perm128(v - c1), dB1 = perm128(c1 + v), mB1 = perm128(-c1 - v);
+        double best = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = k0 + s;
+            const int rowA = k - u, rowB = k + u;
+            const bool mirA = rowA < 0, mirB = rowB > H128;       // uniform
+            const double2* pA = Wb + (mirA ? -rowA : rowA) * T128;
+            const double2* pB = Wb + (mirB ? T128 - rowB : rowB) * T128;
+            const double2 xa0 = pA[mirA ? mA0 : dA0], xa1 = pA[mirA ? mA1 : dA1];
+            const double2 xb0 = pB[mirB ? mB0 : dB0], xb1 = pB[mirB ? mB1 : dB1];
+            // R -= c W1 + conj(c) W2 with W1 = xa or conj(xa), W2 = xb or conj(xb)
+            const double ciA = neg_if(mirA, ci), crA = neg_if(mirA, cr);
+            const double ciB = neg_if(mirB, ci), crB = neg_if(mirB, cr);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double2 x1 = h ? xa1 : xa0, x2 = h ? xb1 : xb0;
+                double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
+                const double sr = x1.x + x2.x, dr = x1.x - x2.x;
+                re = fma(-cr, sr, re);
+                re = fma(ciA, x1.y, re);
+                re = fma(-ciB, x2.y, re);
+                im = fma(-ci, dr, im);
+                im = fma(-crA, x1.y, im);
+                im = fma(-crB, x2.y, im);
+                if (h) R1.set(s, re, im); else R0.set(s, re, im);
+                // eq. 9 key: |R|^2, then column half (0 first), then smaller row
+                const double m2 = sq_add(im, re * re);
+                uint32_t lo = (__double2loint(m2) & 0xFFFFFF00u) | ((uint32_t)(1 - h) << 7) | (uint32_t)(127 - k);
+                int hi = __double2hiint(m2);
+                if (k == 0 || k == H128) {
+                    // rows 0 and 64 represent columns 0..64 only
+                    const bool ok = h == 0 || lane == 0;
+                    hi = ok ? hi : 0;
+                    lo = ok ? lo : 0u;
+                }
+                best = max_f64(best, __hiloint2double(hi, (int)lo));
+            }
+        }
+        // wavefront maximum (see run_wave): magnitude and column half, then
+        // the smallest lane, then (inside the lane) the smallest row
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        uint64_t hits = __ballot(bhi == mhi);
+        int wl = __builtin_ctzll(hits);
+        uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)blo, wl);
+        hits &= hits - 1;
+        while (hits) {
+            const int ln = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const uint32_t l2 = (uint32_t)__builtin_amdgcn_readlane((int)blo, ln);
+            if ((l2 & 0xFFFFFF80u) > (mlo & 0xFFFFFF80u)) { mlo = l2; wl = ln; }
+        }
+        mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)mlo);
+        wl = __builtin_amdgcn_readfirstlane(wl);
+        int wslot = (int)(127 - (mlo & 127u)) - k0;
+        wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
+        const bool whalf = ((mlo >> 7) & 1u) == 0u;
+        const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
+        Xchg<NW128>& x = sh.xchg[it & 1];
+        if (lane == 0) {
+            x.hi[WI] = mhi;
+            x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
+            const double vx = whalf ? wv1.x : wv0.x, vy = whalf ? wv1.y : wv0.y;
+            x.val[WI] = make_double2(vx, vy);
+        }
+        __syncthreads();
+        uint32_t chi[NW128], clo[NW128];
+#pragma unroll
+        for (int w = 0; w < NW128; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+        int bw = 0;
+        uint32_t whi = chi[0], wlo = clo[0];
+#pragma unroll
+        for (int w = 1; w < NW128; ++w) {
+            const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
+            bw = gt ? w : bw;
+            whi = gt ? chi[w] : whi;
+            wlo = gt ? clo[w] : wlo;
+        }
+        bw = __builtin_amdgcn_readfirstlane(bw);
+        wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
+        const double2 wv = x.val[bw];
+        // selected class: grid row u (index l), grid column v (index k)
+        u = 127 - (int)(wlo & 127u);
+        u = u > H128 ? H128 : u;
+        v = (63 - (int)((wlo >> 7) & 63u)) + (((wlo >> 13) & 1u) ? 0 : 64);
+        const bool selfc = (u == 0 || u == H128) && (v == 0 || v == H128);
+        const double cre = wv.x * gW0;
+        const double cim = selfc ? 0.0 : wv.y * gW0;
+        if (WI == 0 && lane == 0) {
+            const size_t r = (size_t)b * K + it;
+            p.sel[r] = v * T128 + u;
+            p.coef[2 * r] = cre;
+            p.coef[2 * r + 1] = cim;
+        }
+        // a self-conjugate class is applied as two half terms (W[k+u] = W[k-u])
+        cr = selfc ? 0.5 * cre : cre;
+        ci = cim;
+    }
+}
+
+// One wavefront: take its rows of R from the LDS spectrum into registers,
+// join the W transform (all waves run the same barriers), then iterate.
+template <int WI, class FW>
+__device__ __forceinline__ void wave128(Shared128& sh, const KParams& p, int b, int tid, int lane,
+                                        double gamma, int flags_pre, FW wval) {
+    constexpr int k0 = row_begin128(WI);
+    constexpr int S = row_begin128(WI + 1) - k0;
+    RegSpec<S> R0, R1;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double2* row = sh.spec + (k0 + s) * T128;
+        const double2 a = row[perm128(lane)], c = row[perm128(lane + 64)];
+        R0.set(s, a.x, a.y);
+        R1.set(s, c.x, c.y);
+    }
+    __syncthreads();                                        // every wave has its rows
+    row_half_spectrum(sh, p.M, p.N, tid, wval);             // W, row half, in LDS
+    const double W0 = sh.spec[0].x;
+    int flags = sh.flags | flags_pre;
+    if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
+    if (flags == 0) run_wave128<WI>(R0, R1, sh, p, b, lane, gamma / W0);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(NT128, 1) void fofse_fwd128_kernel(KParams p) {
+    __shared__ Shared128 sh;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int b = (int)__builtin_amdgcn_workgroup_id_x();
+    const int M = p.M, N = p.N, K = p.K;
+    const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
+    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    for (int i = tid; i < T128; i += NT128) sh.tw[i] = p.twiddle[i];
+    if (tid == 0) sh.flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    __syncthreads();
+    const size_t ab = (size_t)b * M * N;
+    auto support = [&](int i) -> bool {
+        bool a = p.target[i] == 0;
+        if (p.known) a = a && p.known[ab + i] != 0;
+        return a;
+    };
+    // eqs. 4, 7, 8: R from w f (a non-finite known sample flags the block)
+    row_half_spectrum(sh, M, N, tid, [&](int i) -> double {
+        if (!support(i)) return 0.0;
+        const float fv = p.areas[ab + i];
+        if ((__float_as_uint(fv) & 0x7f800000u) == 0x7f800000u) {
+            atomicOr(&sh.flags, FOFSE_BLOCK_NONFINITE);
+            return 0.0;
+        }
+        return p.wtab[i] * (double)fv;
+    });
+    const int flags_pre = sh.flags;
+    auto wval = [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; };
+    switch (wave) {
+        case 0: wave128<0>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 1: wave128<1>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 2: wave128<2>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 3: wave128<3>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 4: wave128<4>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 5: wave128<5>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        case 6: wave128<6>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+        default: wave128<7>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
+    }
+    // flags are final after the W transform (all waves passed its barriers)
+    int flags = sh.flags;
+    const double W0 = sh.spec[0].x;
+    if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
+    if (flags != 0) {          // empty record: the synthesised model is 0
+        for (int it = tid; it < K; it += NT128) {
+            p.sel[(size_t)b * K + it] = 0;
+            p.coef[2 * ((size_t)b * K + it)] = 0.0;
+            p.coef[2 * ((size_t)b * K + it) + 1] = 0.0;
+        }
+    }
+    if (p.status && tid == 0) p.status[b] = flags;
+}
+
+hipError_t launch_fwd128(const KParams& p, hipStream_t stream) {
+    hipLaunchKernelGGL(fofse_fwd128_kernel, dim3(p.n_blocks), dim3(NT128), 0, stream, p);
+    return hipGetLastError();
+}
+
+}  // namespace fofse

@@ -97,6 +97,7 @@ hipError_t launch_weights(const KParams& p, hipStream_t stream);
 hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
                           const Timing& tm);
 hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
+hipError_t launch_fwd128(const KParams& p, hipStream_t stream);
 hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
                            const Timing& tm);
 

@@ -69,3 +69,56 @@ def test_mixed_class_forward_and_adjoint(frame_img, cls_index):
         assert np.abs(ga[i] - adj.f_bar).max() <= 1e-6 * scale
         assert gb[i, 0] == pytest.approx(adj.rho_bar, rel=1e-6, abs=1e-9 * scale)
         assert gb[i, 1] == pytest.approx(adj.gamma_bar, rel=1e-6, abs=1e-9 * scale)
+
+
+def test_mixed_class_128_forward(frame_img):
+    """32 x 32 losses in 64 x 64 areas, 128-point DFT, K = 300 (row-half
+    spectra, eight wavefronts per block)."""
+    plan, areas, target, truth, out, sel, coef, st, ref, f, kn = _run(frame_img, 3, 8, 103)
+    assert np.all(st == 0)
+    ok, div = selection_parity(sel, ref.keys, ref.margin, 1e-6, top_ref=ref.top)
+    assert ok.all(), np.nonzero(~ok)[0]
+    same = np.all(sel == ref.keys, axis=1)
+    tb = target.reshape(-1) == 1
+    err = np.abs(out - ref.g.reshape(len(f), -1)[:, tb]).max(axis=1)
+    assert same.sum() >= 6 and np.all(err[same] <= 1e-3), (same, err)
+    c_ref = np.stack([ref.coef.real, ref.coef.imag], -1)
+    print(f"[gpu] T=128: diverging {int(div.sum())}/{len(f)}, max|dg| {err[same].max():.2e}, "
+          f"max|dc| {np.abs(coef - c_ref)[same].max():.2e}", flush=True)
+
+
+def test_128_irregular_masks_and_flags(frame_img):
+    """T = 128 with irregular support masks, a block without support, a NaN
+    known sample, and the adjoint reporting the size as unsupported."""
+    from paper_2207_01205_amd import fofse as F
+    block, support, T, K = synth.MIXED_CLASSES[3]
+    areas, target, truth, _ = synth.mixed_blocks(frame_img, 77, block, support, 5)
+    rng = np.random.default_rng(5)
+    known = (rng.random(areas.shape) > 0.2).astype(np.uint8)
+    known[1] = 0
+    areas[2, 3, 3] = np.nan
+    known[2, 3, 3] = 1
+    dev = torch.device("cuda", 0)
+    plan = F.Plan(64, 64, T, 60, target, device=0)
+    print("[gpu] T=128 irregular masks and flags", flush=True)
+    out, sel, coef, st = plan.extrapolate(torch.from_numpy(areas).to(dev),
+                                          torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev),
+                                          known=torch.from_numpy(known).to(dev), record=True)
+    torch.cuda.synchronize()
+    out, sel, st = out.cpu().numpy(), sel.cpu().numpy(), st.cpu().numpy()
+    assert st[1] == F.FOFSE_BLOCK_NO_SUPPORT and st[2] == F.FOFSE_BLOCK_NONFINITE
+    assert np.all(out[[1, 2]] == 0) and np.all(sel[[1, 2]] == 0)
+    ok_blocks = [0, 3, 4]
+    f = areas[ok_blocks].astype(np.float64)
+    kn = (known[ok_blocks] * (1 - target)).astype(np.uint8)
+    ref = fofse(f, kn, T, 0.8, 0.5, 60)
+    ok, _ = selection_parity(sel[ok_blocks], ref.keys, ref.margin, 1e-6, top_ref=ref.top)
+    assert ok.all()
+    same = np.all(sel[ok_blocks] == ref.keys, axis=1)
+    err = np.abs(out[ok_blocks] - ref.g.reshape(3, -1)[:, target.reshape(-1) == 1]).max(axis=1)
+    assert np.all(err[same] <= 1e-3)
+    with pytest.raises(F.FofseError):
+        plan.backward(torch.from_numpy(areas).to(dev), torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev),
+                      torch.zeros((5, 60), dtype=torch.int32, device=dev),
+                      torch.zeros((5, 60, 2), dtype=torch.float64, device=dev),
+                      torch.zeros((5, plan.nB), dtype=torch.float32, device=dev))
