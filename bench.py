@@ -98,6 +98,29 @@ def make_tuning_workload(n_train: int, n_held: int):
     return ((cat(0, tr), cat(1, tr), cat(3, tr)), (cat(0, he), cat(1, he), cat(3, he)), parts[0][2])
 
 
+def _frame_img(i):
+    from paper_2207_01205_amd import synth
+    return synth.frame(100 + i)
+
+
+def make_mixed_workload(per_class: int, n_frames: int = 4):
+    """The mixed-size batch: per_class blocks of each size class (4x4, 8x8,
+    16x16, 32x32 losses), at seeded positions of n_frames synthetic 1080p
+    frames, in a seeded order within each class."""
+    from paper_2207_01205_amd import synth
+    with mp.get_context("fork").Pool(min(16, n_frames)) as pool:
+        imgs = pool.map(_frame_img, range(n_frames))
+    classes = []
+    for ci, (block, support, Tc, Kc) in enumerate(synth.MIXED_CLASSES):
+        parts = [synth.mixed_blocks(img, 1000 * ci + j, block, support, per_class // n_frames)
+                 for j, img in enumerate(imgs)]
+        areas = np.concatenate([q[0] for q in parts])
+        order = np.random.default_rng(ci).permutation(len(areas))
+        classes.append({"block": block, "support": support, "T": Tc, "K": Kc,
+                        "areas": np.ascontiguousarray(areas[order]), "target": parts[0][1]})
+    return classes
+
+
 def make_workload(n_frames: int):
     with mp.get_context("fork").Pool(min(16, n_frames, os.cpu_count() or 1)) as pool:
         parts = pool.map(_frame, range(n_frames))
@@ -164,6 +187,106 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+MIXED_SAMPLE = 3       # oracle-checked blocks per size class
+
+
+def _mixed_oracle(args):
+    areas, target, T, K = args
+    from oracle.fofse_dft import fofse
+    kn = np.broadcast_to(1 - target, areas.shape).astype(np.uint8)
+    r = fofse(areas.astype(np.float64), kn, T, RHO, GAMMA, K)
+    return r.keys, r.margin, r.top, r.g.reshape(len(areas), -1)[:, target.reshape(-1) == 1]
+
+
+def mixed_oracle_sample(classes, workers):
+    """FP64 oracle on the first MIXED_SAMPLE blocks of every class."""
+    tasks = [(c["areas"][:MIXED_SAMPLE], c["target"], c["T"], c["K"]) for c in classes]
+    with mp.get_context("fork").Pool(min(workers, len(tasks))) as pool:
+        return pool.map(_mixed_oracle, tasks)
+
+
+def run_mixed(classes, refs, args, dev):
+    """The mixed-size batch: plain (one launch per class, in turn, default
+    organisation) against batched (organisation per class picked by the
+    autotuner, classes on concurrent streams, the whole batch one graph)."""
+    import torch
+    from oracle.fofse_dft import selection_parity
+    from paper_2207_01205_amd import fofse as F
+    from paper_2207_01205_amd.autotune import autotune
+    from paper_2207_01205_amd.mixed import MixedBatch
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    plans, inputs, outs, recs, sts = [], [], [], [], []
+    for c in classes:
+        A = c["areas"].shape[1]
+        plan = F.Plan(A, A, c["T"], c["K"], c["target"], device=0)
+        a = torch.from_numpy(c["areas"]).to(dev)
+        n = a.shape[0]
+        plans.append(plan)
+        inputs.append((a, None))
+        outs.append(torch.empty((n, plan.nB), dtype=torch.float32, device=dev))
+        recs.append((torch.empty((n, c["K"]), dtype=torch.int32, device=dev),
+                     torch.empty((n, c["K"], 2), dtype=torch.float64, device=dev)))
+        sts.append(torch.empty((n,), dtype=torch.int32, device=dev))
+    mb = MixedBatch(plans)
+    n_all = sum(int(x[0].shape[0]) for x in inputs)
+    flops = sum(int(x[0].shape[0]) * flops_per_block(c["T"], c["K"]) for x, c in zip(inputs, classes))
+    steps = max(3, args.steps // 4)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    # plain: default organisation, classes one after the other on one stream
+    for p_ in plans:
+        p_.set_path(F.FOFSE_PATH_AUTO)
+        p_.set_waves(0)
+    t_plain = timed(lambda: mb.extrapolate(inputs, rg, outs, recs, sts, concurrent=False), steps)
+    # autotune each class on a sample of its blocks
+    tuned = {}
+    for c, p_, (a, _) in zip(classes, plans, inputs):
+        times, best = autotune(p_, a, rg)
+        tuned[f"{c['block']}x{c['block']}/T{c['T']}"] = {"choice": best,
+                                                         "ms_per_class": {k: round(v, 4) for k, v in times.items()}}
+    print(f"[bench] autotune: {json.dumps(tuned)}", file=sys.stderr, flush=True)
+    # batched: concurrent classes, captured once and replayed
+    mb.extrapolate(inputs, rg, outs, recs, sts)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mb.extrapolate(inputs, rg, outs, recs, sts)
+    t_batched = timed(graph.replay, steps)
+    torch.cuda.synchronize()
+    parity = []
+    if refs is not None:
+        for c, ref, o, (sel, _), st in zip(classes, refs, outs, recs, sts):
+            keys, margin, top, g_ref = ref
+            s_h = sel[:MIXED_SAMPLE].cpu().numpy()
+            ok, div = selection_parity(s_h, keys, margin, 1e-6, top_ref=top)
+            same = np.all(s_h == keys, axis=1)
+            err = np.abs(o[:MIXED_SAMPLE].cpu().numpy() - g_ref).max(axis=1)
+            parity.append({"class": f"{c['block']}x{c['block']}", "blocks": MIXED_SAMPLE,
+                           "rule_ok": bool(ok.all()), "diverging": int(div.sum()),
+                           "max_abs_dg": float(err[same].max()) if same.any() else None,
+                           "status_nonzero": int((st != 0).sum().item())})
+    del graph
+    return {"workload": "mixed-size batch: 4x4/8x8/16x16/32x32 losses, areas 12/24/48/64, "
+                        "T 16/32/64/128, K 32/64/200/300, one quarter each, synthetic 1080p frames",
+            "blocks": n_all, "flop_per_batch": flops,
+            "plain": {"ms_per_batch": t_plain * 1e3, "blocks_per_s": n_all / t_plain,
+                      "fp64_peak_frac": flops / t_plain / FP64_VECTOR_PEAK},
+            "batched": {"ms_per_batch": t_batched * 1e3, "blocks_per_s": n_all / t_batched,
+                        "fp64_peak_frac": flops / t_batched / FP64_VECTOR_PEAK,
+                        "organisation": tuned},
+            "sample_parity": parity}
 
 
 def run_tuning(data, args, dev):
@@ -257,6 +380,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--mixed", type=int, default=25000, metavar="PER_CLASS",
+                    help="blocks per size class of the mixed-size batch (0 = skip)")
     ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
                     help="also fit (rho_hat, gamma) by Adam for STEPS steps on 64 synthetic "
                          "3840x2160 frames with 5%% block loss, one captured graph per step "
@@ -280,6 +405,10 @@ def main():
     # everything that forks runs before the GPU is initialised
     areas, known, target, truth = make_workload(args.frames)
     tune_data = make_tuning_workload(args.tune_frames, 8) if args.tune > 0 else None
+    mixed_data = make_mixed_workload(args.mixed) if args.mixed > 0 else None
+    mixed_ref = None
+    if mixed_data is not None and not args.no_cpu_baseline:
+        mixed_ref = mixed_oracle_sample(mixed_data, min(16, len(os.sched_getaffinity(0))))
     n = len(areas)
     base = None
     if not args.no_cpu_baseline:
@@ -433,6 +562,7 @@ def main():
         del graph
 
     tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
+    mixed = run_mixed(mixed_data, mixed_ref, args, dev) if mixed_data is not None else None
 
     # final full-batch pass for the outputs checked below
     step()
@@ -477,6 +607,8 @@ def main():
     }
     if tuning is not None:
         result["tuning"] = tuning
+    if mixed is not None:
+        result["mixed"] = mixed
     if base is not None:
         info, ref = base
         info["sample_parity"] = sample_parity(ref, out_h, sel_h)

@@ -51,7 +51,8 @@ typedef enum {
  *   area_h, area_w : M, N, the area size (1 <= M, N <= fft_size).  The isotropic
  *                    model is centred at ((M-1)/2, (N-1)/2) (eq. 15).
  *   fft_size       : T, the DFT size (the paper's FFT size, Section 3).
- *                    Supported: 16, 32 and 64.
+ *                    Supported: 16, 32, 64 and 128 (128: area at most
+ *                    64 x 64; no adjoint).
  *   iterations     : K >= 0, the number of iterations (the paper's I, Table 1),
  *                    at most 4096.
  *   target_mask    : host, M*N bytes row-major, non-zero on the missing area B.
@@ -141,6 +142,18 @@ fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
                                      const double* d_rho_gamma, float* d_out,
                                      int32_t* d_sel, double* d_coef,
                                      int32_t* d_status, void* stream);
+
+/*
+ * Wavefronts per block of the split path (FOFSE_PATH_SPLIT, and AUTO when it
+ * picks the split path); 0 restores the default.  Built: T = 16: 1 (default),
+ * 2; T = 32: 1, 2 (default), 4; T = 64: 2, 4 (default), 8; T = 128: 8 (the
+ * only choice).  More wavefronts hold fewer rows of R each (fewer registers,
+ * more exchange per iteration).  Results are the same bits for every choice of
+ * a given FFT size except for the order of the transform's rounding.
+ * Returns FOFSE_ERR_ARG for a NULL plan or a negative count,
+ * FOFSE_ERR_UNSUPPORTED for a count not built for the plan's FFT size.
+ */
+fofse_status fofse_set_waves(fofse_plan plan, int32_t waves);
 
 /*
  * Profiling hook.  With timing enabled, every fofse_extrapolate_batch and

@@ -16,6 +16,7 @@ struct fofse_plan_s {
     int device = 0;
     int n_cu = 0;
     int path = FOFSE_PATH_AUTO;
+    int waves = 0;                  // split path: wavefronts per block (0 = default)
     int M = 0, N = 0, T = 0, K = 0, nB = 0;
     uint8_t* d_target = nullptr;
     int32_t* d_bpix = nullptr;
@@ -220,6 +221,13 @@ fofse_status fofse_set_path(fofse_plan p, int32_t path) {
     return FOFSE_OK;
 }
 
+fofse_status fofse_set_waves(fofse_plan p, int32_t waves) {
+    if (!p || waves < 0) return FOFSE_ERR_ARG;
+    if (!fofse::split_waves_built(p->T, waves)) return FOFSE_ERR_UNSUPPORTED;
+    p->waves = waves;
+    return FOFSE_OK;
+}
+
 fofse_status fofse_set_timing(fofse_plan p, int32_t enable) {
     if (!p) return FOFSE_ERR_ARG;
     DeviceGuard guard(p->device);
@@ -278,6 +286,7 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
     k.sel = d_sel;
     k.coef = d_coef;
     k.status = d_status;
+    k.waves = p->waves;
     if (!d_sel || !d_coef) {
         const fofse_status rs = ensure_record(p, n_blocks);
         if (rs != FOFSE_OK) return rs;

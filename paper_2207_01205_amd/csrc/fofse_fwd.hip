@@ -185,6 +185,17 @@ static hipError_t launch_fwd(const KParams& p, hipStream_t stream) {
 
 int max_target_samples(int T) { return T * T; }
 
+bool split_waves_built(int T, int waves) {
+    if (waves == 0) return true;
+    switch (T) {
+        case 16: return waves == 1 || waves == 2;
+        case 32: return waves == 1 || waves == 2 || waves == 4;
+        case 64: return waves == 2 || waves == 4 || waves == 8;
+        case 128: return waves == 8;
+        default: return false;
+    }
+}
+
 // eq. 15: isotropic model rho_hat ** dist((m, n), ((M-1)/2, (N-1)/2)) for every
 // sample of the area (the mask of eq. 4 is applied where it is used).  Kept out
 // of the main kernels so that they contain no library calls.
@@ -211,10 +222,13 @@ hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm
     hipError_t e = launch_weights(p, stream);
     if (e != hipSuccess) return e;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
+    const int nw = p.waves;
     if (p.T == 128) e = launch_fwd128(p, stream);
-    else if (p.T == 64) e = launch_fwd<64, kWaves64>(p, stream);
-    else if (p.T == 32) e = launch_fwd<32, kWaves32>(p, stream);
-    else e = launch_fwd<16, kWaves16>(p, stream);
+    else if (p.T == 64) e = nw == 2 ? launch_fwd<64, 2>(p, stream) : nw == 8 ? launch_fwd<64, 8>(p, stream)
+                                    : launch_fwd<64, kWaves64>(p, stream);
+    else if (p.T == 32) e = nw == 1 ? launch_fwd<32, 1>(p, stream) : nw == 4 ? launch_fwd<32, 4>(p, stream)
+                                    : launch_fwd<32, kWaves32>(p, stream);
+    else e = nw == 2 ? launch_fwd<16, 2>(p, stream) : launch_fwd<16, kWaves16>(p, stream);
     if (e != hipSuccess) return e;
     if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
     return launch_synthesis(p, stream);

@@ -18,8 +18,8 @@
 //     the direct and the mirrored read is uniform (it depends on the slot's row
 //     and the selected u only), and the conjugation is folded into the signs of
 //     the coefficient.
-//   * Columns are stored in the FFT's output order; each lane maps its four
-//     column indices once per iteration.
+//   * After the transforms each wavefront puts its rows in natural column order,
+//     so that neighbouring lanes read neighbouring entries of W.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,7 +46,7 @@ __device__ __forceinline__ int perm128(int k) { return FftPlan<T128>::perm(k & (
 __device__ __forceinline__ double neg_if(bool c, double x) { return c ? -x : x; }
 
 struct Shared128 {
-    double2 spec[ROWS128 * T128];   // row half of a spectrum (FFT column order)
+    double2 spec[ROWS128 * T128];   // row half of a spectrum, natural column order
     double2 tw[T128];
     Xchg<NW128> xchg[2];
     int flags;
@@ -94,6 +94,17 @@ __device__ __forceinline__ void row_half_spectrum(Shared128& sh, int M, int N, i
     __syncthreads();
     fft_stage_b<T128, NT128>(sh.spec, ROWS128, T128, 1, tid);
     __syncthreads();
+    // FFT output order -> natural column order, one row per wavefront: all lanes
+    // read the row before any lane writes it (a wavefront's LDS operations run
+    // in program order), so no barrier is needed inside a row
+    const int lane = tid & 63;
+    for (int r = tid >> 6; r < ROWS128; r += NW128) {
+        double2* row = sh.spec + r * T128;
+        const double2 a = row[perm128(lane)], c = row[perm128(lane + 64)];
+        row[lane] = a;
+        row[lane + 64] = c;
+    }
+    __syncthreads();
 }
 
 // One wavefront's rows [k0, k0 + S) of the K iterations.
@@ -110,9 +121,11 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_b
     double cr = 0.0, ci = 0.0;
     const int c0 = lane, c1 = lane + 64;
     for (int it = 0; it < K; ++it) {
-        // permuted column indices of the four read forms for both columns
-        const int dA0 = perm128(c0 - v), mA0 = perm128(v - c0), dB0 = perm128(c0 + v), mB0 = perm128(-c0 - v);
-        const int dA1 = perm128(c1 - v), mA1 = perm128(v - c1), dB1 = perm128(c1 + v), mB1 = perm128(-c1 - v);
+        // column indices of the four read forms for both columns
+        const int dA0 = (c0 - v) & (T128 - 1), mA0 = (v - c0) & (T128 - 1);
+        const int dB0 = (c0 + v) & (T128 - 1), mB0 = (-c0 - v) & (T128 - 1);
+        const int dA1 = (c1 - v) & (T128 - 1), mA1 = (v - c1) & (T128 - 1);
+        const int dB1 = (c1 + v) & (T128 - 1), mB1 = (-c1 - v) & (T128 - 1);
         double best = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -224,7 +237,7 @@ __device__ __forceinline__ void wave128(Shared128& sh, const KParams& p, int b, 
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double2* row = sh.spec + (k0 + s) * T128;
-        const double2 a = row[perm128(lane)], c = row[perm128(lane + 64)];
+        const double2 a = row[lane], c = row[lane + 64];
         R0.set(s, a.x, a.y);
         R1.set(s, c.x, c.y);
     }

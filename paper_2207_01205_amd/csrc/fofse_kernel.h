@@ -31,7 +31,11 @@ struct KParams {
     int32_t* sel;            // [n][K] selection record (caller's or plan workspace)
     double* coef;            // [n][K][2] coefficient record
     int32_t* status;         // [n] or null
+    int waves;               // split path: wavefronts per block (0 = default)
 };
+
+// Wavefronts per block the split path is built for, per FFT size.
+bool split_waves_built(int T, int waves);
 
 // Arguments of the adjoint (backward) kernels.
 struct BParams {

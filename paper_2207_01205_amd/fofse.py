@@ -31,7 +31,8 @@ FOFSE_PATH_AUTO = 0
 FOFSE_PATH_SPLIT = 1
 FOFSE_PATH_GROUPED = 2
 
-EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_extrapolate_batch",
+EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves",
+            "fofse_extrapolate_batch",
             "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
             "fofse_status_str")
 
@@ -69,6 +70,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_target_count.restype = ctypes.c_int32
     L.fofse_set_path.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_path.restype = ctypes.c_int
+    L.fofse_set_waves.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_waves.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
     L.fofse_backward.argtypes = [vp, ctypes.c_int32] + [vp] * 10
@@ -115,6 +118,12 @@ def fofse_set_path(plan: int, path: int) -> None:
     st = load_library().fofse_set_path(plan, int(path))
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_set_path")
+
+
+def fofse_set_waves(plan: int, waves: int) -> None:
+    st = load_library().fofse_set_waves(plan, int(waves))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_waves")
 
 
 def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int,
@@ -175,6 +184,9 @@ class Plan:
 
     def set_path(self, path: int):
         fofse_set_path(self.handle, path)
+
+    def set_waves(self, waves: int):
+        fofse_set_waves(self.handle, waves)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -122,3 +122,54 @@ def test_128_irregular_masks_and_flags(frame_img):
                       torch.zeros((5, 60), dtype=torch.int32, device=dev),
                       torch.zeros((5, 60, 2), dtype=torch.float64, device=dev),
                       torch.zeros((5, plan.nB), dtype=torch.float32, device=dev))
+
+
+def test_mixed_batch_graph_and_autotune(frame_img):
+    """All four classes in one captured graph on concurrent streams give the
+    same bits as the classes run one after another; the autotuner's choice
+    stays within the parity rule."""
+    from paper_2207_01205_amd import fofse as F
+    from paper_2207_01205_amd.autotune import autotune
+    from paper_2207_01205_amd.mixed import MixedBatch
+    dev = torch.device("cuda", 0)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    plans, inputs, outs, recs, data = [], [], [], [], []
+    for ci, (block, support, T, K) in enumerate(synth.MIXED_CLASSES):
+        areas, target, _, _ = synth.mixed_blocks(frame_img, 500 + ci, block, support, 40)
+        A = areas.shape[1]
+        plans.append(F.Plan(A, A, T, K, target, device=0))
+        a = torch.from_numpy(areas).to(dev)
+        inputs.append((a, None))
+        outs.append(torch.empty((40, plans[-1].nB), dtype=torch.float32, device=dev))
+        recs.append((torch.empty((40, K), dtype=torch.int32, device=dev),
+                     torch.empty((40, K, 2), dtype=torch.float64, device=dev)))
+        data.append((areas, target, T, K))
+    print("[gpu] mixed batch: 4 classes x 40 blocks, sequential vs graph", flush=True)
+    mb = MixedBatch(plans)
+    mb.extrapolate(inputs, rg, outs, recs, concurrent=False)
+    torch.cuda.synchronize()
+    seq = [(o.cpu().numpy().copy(), r[0].cpu().numpy().copy()) for o, r in zip(outs, recs)]
+    graph = torch.cuda.CUDAGraph()
+    mb.extrapolate(inputs, rg, outs, recs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        mb.extrapolate(inputs, rg, outs, recs)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        for (o_seq, s_seq), o, r in zip(seq, outs, recs):
+            assert np.array_equal(o.cpu().numpy(), o_seq) and np.array_equal(r[0].cpu().numpy(), s_seq)
+    del graph
+    # autotune the 16x16 class and check the chosen organisation against the oracle
+    areas, target, T, K = data[2]
+    times, best = autotune(plans[2], inputs[2][0], rg)
+    print(f"[gpu] autotune T=64: {best} {times}", flush=True)
+    out, sel, coef, st = plans[2].extrapolate(inputs[2][0], rg, record=True)
+    torch.cuda.synchronize()
+    f = areas[:12].astype(np.float64)
+    kn = np.broadcast_to(1 - target, f.shape).astype(np.uint8)
+    ref = fofse(f, kn, T, 0.8, 0.5, K)
+    ok, _ = selection_parity(sel.cpu().numpy()[:12], ref.keys, ref.margin, 1e-6, top_ref=ref.top)
+    assert ok.all()
