@@ -146,8 +146,8 @@ fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
 /*
  * Wavefronts per block of the split path (FOFSE_PATH_SPLIT, and AUTO when it
  * picks the split path); 0 restores the default.  Built: T = 16: 1 (default),
- * 2; T = 32: 1, 2 (default), 4; T = 64: 2, 4 (default), 8; T = 128: 8 (the
- * only choice).  More wavefronts hold fewer rows of R each (fewer registers,
+ * 2; T = 32: 1, 2 (default), 4; T = 64: 2, 4 (default), 8; T = 128: 8 (default),
+ * 16.  More wavefronts hold fewer rows of R each (fewer registers,
  * more exchange per iteration).  Results are the same bits for every choice of
  * a given FFT size except for the order of the transform's rounding.
  * Returns FOFSE_ERR_ARG for a NULL plan or a negative count,

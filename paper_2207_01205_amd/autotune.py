@@ -13,7 +13,7 @@ from __future__ import annotations
 from . import fofse as F
 
 # wavefronts per block built for the split path, per FFT size
-SPLIT_WAVES = {16: (1, 2), 32: (1, 2, 4), 64: (2, 4, 8), 128: (8,)}
+SPLIT_WAVES = {16: (1, 2), 32: (1, 2, 4), 64: (2, 4, 8), 128: (8, 16)}
 
 
 def candidates(T: int):

@@ -191,7 +191,7 @@ bool split_waves_built(int T, int waves) {
         case 16: return waves == 1 || waves == 2;
         case 32: return waves == 1 || waves == 2 || waves == 4;
         case 64: return waves == 2 || waves == 4 || waves == 8;
-        case 128: return waves == 8;
+        case 128: return waves == 8 || waves == 16;
         default: return false;
     }
 }

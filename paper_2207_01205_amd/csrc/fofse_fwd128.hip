@@ -11,8 +11,8 @@
 //     over n evaluated only for l = 0..64 (the real input makes the other rows
 //     redundant), then 128-point FFTs over m for each of those 65 rows.  The
 //     result, the row half of the spectrum, occupies 65 x 128 x 16 B = 133 KB.
-//   * R (rows 0..64) lives in registers: 8 wavefronts share the rows, every
-//     lane holds columns lane and lane + 64.
+//   * R (rows 0..64) lives in registers: 8 or 16 wavefronts share the rows,
+//     every lane holds columns lane and lane + 64.
 //   * W stays in LDS as its row half.  A read W[r][c] with r outside 0..64 is
 //     conj(W[-r][-c]) (w is real); for every register slot the choice between
 //     the direct and the mirrored read is uniform (it depends on the slot's row
@@ -34,47 +34,48 @@ namespace {
 
 constexpr int T128 = 128;
 constexpr int H128 = 64;
-constexpr int NW128 = 8;
-constexpr int NT128 = NW128 * 64;
 constexpr int ROWS128 = H128 + 1;
 
-__host__ __device__ constexpr int row_begin128(int w) { return (w * ROWS128 + NW128 - 1) / NW128; }
-constexpr int SMAX128 = row_begin128(1) - row_begin128(0);
+template <int NW>
+__host__ __device__ constexpr int row_begin128(int w) { return (w * ROWS128 + NW - 1) / NW; }
 
 __device__ __forceinline__ int perm128(int k) { return FftPlan<T128>::perm(k & (T128 - 1)); }
 
 __device__ __forceinline__ double neg_if(bool c, double x) { return c ? -x : x; }
 
+template <int NW>
 struct Shared128 {
     double2 spec[ROWS128 * T128];   // row half of a spectrum, natural column order
     double2 tw[T128];
-    Xchg<NW128> xchg[2];
+    Xchg<NW> xchg[2];
     int flags;
 };
 
 // Spectrum rows l = 0..64 of x (area values from ``val``, transposed placement)
 // into sh.spec: direct DFT over n for l <= 64, then 128-point FFTs over m.
 // ``val(i)`` gives the value of area sample i = m * N + n (0 outside A).
-template <class F>
-__device__ __forceinline__ void row_half_spectrum(Shared128& sh, int M, int N, int tid, F val) {
+template <int NW, class F>
+__device__ __forceinline__ void row_half_spectrum(Shared128<NW>& sh, int M, int N, int tid, F val) {
+    constexpr int NT = NW * 64;
+    constexpr int NJ = (ROWS128 + NW - 1) / NW;             // output rows per thread
     double* xs = reinterpret_cast<double*>(sh.spec);      // staging xs[n * 64 + m]
-    for (int i = tid; i < 64 * 64; i += NT128) xs[i] = 0.0;
+    for (int i = tid; i < 64 * 64; i += NT) xs[i] = 0.0;
     __syncthreads();
-    for (int i = tid; i < M * N; i += NT128) {
+    for (int i = tid; i < M * N; i += NT) {
         const int m = i / N, n = i - m * N;
         xs[n * 64 + m] = val(i);
     }
     __syncthreads();
-    // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128), l = lg + 8 j
+    // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128), l = lg + NW j
     const int m = tid & 63, lg = tid >> 6;
-    double2 acc[9];
+    double2 acc[NJ];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) acc[j] = make_double2(0.0, 0.0);
+    for (int j = 0; j < NJ; ++j) acc[j] = make_double2(0.0, 0.0);
     for (int n = 0; n < N; ++n) {
         const double x = xs[n * 64 + m];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const int l = lg + 8 * j;
+        for (int j = 0; j < NJ; ++j) {
+            const int l = lg + NW * j;
             const double2 t = sh.tw[(l * n) & (T128 - 1)];
             acc[j].x = fma(x, t.x, acc[j].x);
             acc[j].y = fma(x, t.y, acc[j].y);
@@ -82,23 +83,23 @@ __device__ __forceinline__ void row_half_spectrum(Shared128& sh, int M, int N, i
     }
     __syncthreads();                                        // staging consumed
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        const int l = lg + 8 * j;
+    for (int j = 0; j < NJ; ++j) {
+        const int l = lg + NW * j;
         if (l <= H128) {
             sh.spec[l * T128 + m] = acc[j];
             sh.spec[l * T128 + 64 + m] = make_double2(0.0, 0.0);
         }
     }
     __syncthreads();
-    fft_stage_a<T128, NT128>(sh.spec, sh.tw, ROWS128, T128, 1, tid);
+    fft_stage_a<T128, NT>(sh.spec, sh.tw, ROWS128, T128, 1, tid);
     __syncthreads();
-    fft_stage_b<T128, NT128>(sh.spec, ROWS128, T128, 1, tid);
+    fft_stage_b<T128, NT>(sh.spec, ROWS128, T128, 1, tid);
     __syncthreads();
     // FFT output order -> natural column order, one row per wavefront: all lanes
     // read the row before any lane writes it (a wavefront's LDS operations run
     // in program order), so no barrier is needed inside a row
     const int lane = tid & 63;
-    for (int r = tid >> 6; r < ROWS128; r += NW128) {
+    for (int r = tid >> 6; r < ROWS128; r += NW) {
         double2* row = sh.spec + r * T128;
         const double2 a = row[perm128(lane)], c = row[perm128(lane + 64)];
         row[lane] = a;
@@ -108,13 +109,13 @@ __device__ __forceinline__ void row_half_spectrum(Shared128& sh, int M, int N, i
 }
 
 // One wavefront's rows [k0, k0 + S) of the K iterations.
-template <int WI>
-__device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_begin128(WI)>& R0,
-                                            RegSpec<row_begin128(WI + 1) - row_begin128(WI)>& R1,
-                                            Shared128& sh, const KParams& p, int b, int lane,
+template <int NW, int WI>
+__device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
+                                            RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
+                                            Shared128<NW>& sh, const KParams& p, int b, int lane,
                                             double gW0) {
-    constexpr int k0 = row_begin128(WI);
-    constexpr int S = row_begin128(WI + 1) - k0;
+    constexpr int k0 = row_begin128<NW>(WI);
+    constexpr int S = row_begin128<NW>(WI + 1) - k0;
     const int K = p.K;
     const double2* Wb = sh.spec;
     int u = 0, v = 0;
@@ -126,43 +127,68 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_b
         const int dB0 = (c0 + v) & (T128 - 1), mB0 = (-c0 - v) & (T128 - 1);
         const int dA1 = (c1 - v) & (T128 - 1), mA1 = (v - c1) & (T128 - 1);
         const int dB1 = (c1 + v) & (T128 - 1), mB1 = (-c1 - v) & (T128 - 1);
+        // The reads of a slot depend only on its row and on (u, v): chunks of CH
+        // slots, the reads of chunk q + 1 issued before chunk q is computed.
+        constexpr int CH = 2;
+        constexpr int NC = (S + CH - 1) / CH;
+        double2 xa[2][CH][2], xb[2][CH][2];     // [buffer][slot of the chunk][column half]
+        auto load = [&](int q, int bf) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int s = q * CH + j;
+                if (s < S) {
+                    const int k = k0 + s;
+                    const int rowA = k - u, rowB = k + u;
+                    const bool mirA = rowA < 0, mirB = rowB > H128;   // uniform
+                    const double2* pA = Wb + (mirA ? -rowA : rowA) * T128;
+                    const double2* pB = Wb + (mirB ? T128 - rowB : rowB) * T128;
+                    xa[bf][j][0] = pA[mirA ? mA0 : dA0];
+                    xa[bf][j][1] = pA[mirA ? mA1 : dA1];
+                    xb[bf][j][0] = pB[mirB ? mB0 : dB0];
+                    xb[bf][j][1] = pB[mirB ? mB1 : dB1];
+                }
+            }
+        };
+        load(0, 0);
         double best = 0.0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 + s;
-            const int rowA = k - u, rowB = k + u;
-            const bool mirA = rowA < 0, mirB = rowB > H128;       // uniform
-            const double2* pA = Wb + (mirA ? -rowA : rowA) * T128;
-            const double2* pB = Wb + (mirB ? T128 - rowB : rowB) * T128;
-            const double2 xa0 = pA[mirA ? mA0 : dA0], xa1 = pA[mirA ? mA1 : dA1];
-            const double2 xb0 = pB[mirB ? mB0 : dB0], xb1 = pB[mirB ? mB1 : dB1];
-            // R -= c W1 + conj(c) W2 with W1 = xa or conj(xa), W2 = xb or conj(xb)
-            const double ciA = neg_if(mirA, ci), crA = neg_if(mirA, cr);
-            const double ciB = neg_if(mirB, ci), crB = neg_if(mirB, cr);
+        for (int q = 0; q < NC; ++q) {
+            if (q + 1 < NC) load(q + 1, (q + 1) & 1);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const double2 x1 = h ? xa1 : xa0, x2 = h ? xb1 : xb0;
-                double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
-                const double sr = x1.x + x2.x, dr = x1.x - x2.x;
-                re = fma(-cr, sr, re);
-                re = fma(ciA, x1.y, re);
-                re = fma(-ciB, x2.y, re);
-                im = fma(-ci, dr, im);
-                im = fma(-crA, x1.y, im);
-                im = fma(-crB, x2.y, im);
-                if (h) R1.set(s, re, im); else R0.set(s, re, im);
-                // eq. 9 key: |R|^2, then column half (0 first), then smaller row
-                const double m2 = sq_add(im, re * re);
-                uint32_t lo = (__double2loint(m2) & 0xFFFFFF00u) | ((uint32_t)(1 - h) << 7) | (uint32_t)(127 - k);
-                int hi = __double2hiint(m2);
-                if (k == 0 || k == H128) {
-                    // rows 0 and 64 represent columns 0..64 only
-                    const bool ok = h == 0 || lane == 0;
-                    hi = ok ? hi : 0;
-                    lo = ok ? lo : 0u;
+            for (int j = 0; j < CH; ++j) {
+                const int s = q * CH + j;
+                if (s >= S) break;
+                const int k = k0 + s;
+                const bool mirA = k - u < 0, mirB = k + u > H128;
+                // R -= c W1 + conj(c) W2 with W1 = xa or conj(xa), W2 = xb or conj(xb)
+                const double ciA = neg_if(mirA, ci), crA = neg_if(mirA, cr);
+                const double ciB = neg_if(mirB, ci), crB = neg_if(mirB, cr);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double2 x1 = xa[q & 1][j][h], x2 = xb[q & 1][j][h];
+                    double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
+                    const double sr = x1.x + x2.x, dr = x1.x - x2.x;
+                    re = fma(-cr, sr, re);
+                    re = fma(ciA, x1.y, re);
+                    re = fma(-ciB, x2.y, re);
+                    im = fma(-ci, dr, im);
+                    im = fma(-crA, x1.y, im);
+                    im = fma(-crB, x2.y, im);
+                    if (h) R1.set(s, re, im); else R0.set(s, re, im);
+                    // eq. 9 key: |R|^2, then column half (0 first), then smaller row
+                    const double m2 = sq_add(im, re * re);
+                    uint32_t lo = (__double2loint(m2) & 0xFFFFFF00u) | ((uint32_t)(1 - h) << 7) | (uint32_t)(127 - k);
+                    int hi = __double2hiint(m2);
+                    if (k == 0 || k == H128) {
+                        // rows 0 and 64 represent columns 0..64 only
+                        const bool ok = h == 0 || lane == 0;
+                        hi = ok ? hi : 0;
+                        lo = ok ? lo : 0u;
+                    }
+                    best = max_f64(best, __hiloint2double(hi, (int)lo));
                 }
-                best = max_f64(best, __hiloint2double(hi, (int)lo));
             }
+            if constexpr (NC > 1) __builtin_amdgcn_sched_barrier(0);
         }
         // wavefront maximum (see run_wave): magnitude and column half, then
         // the smallest lane, then (inside the lane) the smallest row
@@ -184,7 +210,7 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_b
         wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
         const bool whalf = ((mlo >> 7) & 1u) == 0u;
         const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
-        Xchg<NW128>& x = sh.xchg[it & 1];
+        Xchg<NW>& x = sh.xchg[it & 1];
         if (lane == 0) {
             x.hi[WI] = mhi;
             x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
@@ -192,13 +218,13 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_b
             x.val[WI] = make_double2(vx, vy);
         }
         __syncthreads();
-        uint32_t chi[NW128], clo[NW128];
+        uint32_t chi[NW], clo[NW];
 #pragma unroll
-        for (int w = 0; w < NW128; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+        for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
         int bw = 0;
         uint32_t whi = chi[0], wlo = clo[0];
 #pragma unroll
-        for (int w = 1; w < NW128; ++w) {
+        for (int w = 1; w < NW; ++w) {
             const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
             bw = gt ? w : bw;
             whi = gt ? chi[w] : whi;
@@ -228,11 +254,11 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128(WI + 1) - row_b
 
 // One wavefront: take its rows of R from the LDS spectrum into registers,
 // join the W transform (all waves run the same barriers), then iterate.
-template <int WI, class FW>
-__device__ __forceinline__ void wave128(Shared128& sh, const KParams& p, int b, int tid, int lane,
+template <int NW, int WI, class FW>
+__device__ __forceinline__ void wave128(Shared128<NW>& sh, const KParams& p, int b, int tid, int lane,
                                         double gamma, int flags_pre, FW wval) {
-    constexpr int k0 = row_begin128(WI);
-    constexpr int S = row_begin128(WI + 1) - k0;
+    constexpr int k0 = row_begin128<NW>(WI);
+    constexpr int S = row_begin128<NW>(WI + 1) - k0;
     RegSpec<S> R0, R1;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -246,20 +272,32 @@ __device__ __forceinline__ void wave128(Shared128& sh, const KParams& p, int b, 
     const double W0 = sh.spec[0].x;
     int flags = sh.flags | flags_pre;
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
-    if (flags == 0) run_wave128<WI>(R0, R1, sh, p, b, lane, gamma / W0);
+    if (flags == 0) run_wave128<NW, WI>(R0, R1, sh, p, b, lane, gamma / W0);
+}
+
+// dispatch wave w to its specialised instance
+template <int NW, int WI, class FW>
+__device__ __forceinline__ void wave128_dispatch(int w, Shared128<NW>& sh, const KParams& p, int b, int tid,
+                                                 int lane, double gamma, int flags_pre, FW wval) {
+    if constexpr (WI < NW) {
+        if (w == WI) wave128<NW, WI>(sh, p, b, tid, lane, gamma, flags_pre, wval);
+        else wave128_dispatch<NW, WI + 1>(w, sh, p, b, tid, lane, gamma, flags_pre, wval);
+    }
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(NT128, 1) void fofse_fwd128_kernel(KParams p) {
-    __shared__ Shared128 sh;
+template <int NW>
+__global__ __launch_bounds__(NW * 64, 1) void fofse_fwd128_kernel(KParams p) {
+    constexpr int NT = NW * 64;
+    __shared__ Shared128<NW> sh;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     const int lane = tid & 63, wave = tid >> 6;
     const int b = (int)__builtin_amdgcn_workgroup_id_x();
     const int M = p.M, N = p.N, K = p.K;
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && param_ok(gamma);
-    for (int i = tid; i < T128; i += NT128) sh.tw[i] = p.twiddle[i];
+    for (int i = tid; i < T128; i += NT) sh.tw[i] = p.twiddle[i];
     if (tid == 0) sh.flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
     const size_t ab = (size_t)b * M * N;
@@ -280,22 +318,13 @@ __global__ __launch_bounds__(NT128, 1) void fofse_fwd128_kernel(KParams p) {
     });
     const int flags_pre = sh.flags;
     auto wval = [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; };
-    switch (wave) {
-        case 0: wave128<0>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 1: wave128<1>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 2: wave128<2>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 3: wave128<3>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 4: wave128<4>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 5: wave128<5>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        case 6: wave128<6>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-        default: wave128<7>(sh, p, b, tid, lane, gamma, flags_pre, wval); break;
-    }
+    wave128_dispatch<NW, 0>(wave, sh, p, b, tid, lane, gamma, flags_pre, wval);
     // flags are final after the W transform (all waves passed its barriers)
     int flags = sh.flags;
     const double W0 = sh.spec[0].x;
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
     if (flags != 0) {          // empty record: the synthesised model is 0
-        for (int it = tid; it < K; it += NT128) {
+        for (int it = tid; it < K; it += NT) {
             p.sel[(size_t)b * K + it] = 0;
             p.coef[2 * ((size_t)b * K + it)] = 0.0;
             p.coef[2 * ((size_t)b * K + it) + 1] = 0.0;
@@ -305,7 +334,10 @@ __global__ __launch_bounds__(NT128, 1) void fofse_fwd128_kernel(KParams p) {
 }
 
 hipError_t launch_fwd128(const KParams& p, hipStream_t stream) {
-    hipLaunchKernelGGL(fofse_fwd128_kernel, dim3(p.n_blocks), dim3(NT128), 0, stream, p);
+    if (p.waves == 16)
+        hipLaunchKernelGGL(fofse_fwd128_kernel<16>, dim3(p.n_blocks), dim3(16 * 64), 0, stream, p);
+    else
+        hipLaunchKernelGGL(fofse_fwd128_kernel<8>, dim3(p.n_blocks), dim3(8 * 64), 0, stream, p);
     return hipGetLastError();
 }
 

@@ -19,14 +19,15 @@ def frame_img():
     return synth.frame(11)
 
 
-def _run(frame_img, cls_index, n, seed):
+def _run(frame_img, cls_index, n, seed, waves=0):
     from paper_2207_01205_amd.fofse import Plan
     block, support, T, K = synth.MIXED_CLASSES[cls_index]
     areas, target, truth, _ = synth.mixed_blocks(frame_img, seed, block, support, n)
     A = areas.shape[1]
-    print(f"[gpu] mixed class {block}x{block}: n={n} area={A} T={T} K={K}", flush=True)
+    print(f"[gpu] mixed class {block}x{block}: n={n} area={A} T={T} K={K} waves={waves}", flush=True)
     dev = torch.device("cuda", 0)
     plan = Plan(A, A, T, K, target, device=0)
+    plan.set_waves(waves)
     a = torch.from_numpy(areas).to(dev)
     rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
     out, sel, coef, st = plan.extrapolate(a, rg, record=True)
@@ -71,10 +72,11 @@ def test_mixed_class_forward_and_adjoint(frame_img, cls_index):
         assert gb[i, 1] == pytest.approx(adj.gamma_bar, rel=1e-6, abs=1e-9 * scale)
 
 
-def test_mixed_class_128_forward(frame_img):
+@pytest.mark.parametrize("waves", [8, 16])
+def test_mixed_class_128_forward(frame_img, waves):
     """32 x 32 losses in 64 x 64 areas, 128-point DFT, K = 300 (row-half
-    spectra, eight wavefronts per block)."""
-    plan, areas, target, truth, out, sel, coef, st, ref, f, kn = _run(frame_img, 3, 8, 103)
+    spectra, 8 or 16 wavefronts per block)."""
+    plan, areas, target, truth, out, sel, coef, st, ref, f, kn = _run(frame_img, 3, 8, 103, waves)
     assert np.all(st == 0)
     ok, div = selection_parity(sel, ref.keys, ref.margin, 1e-6, top_ref=ref.top)
     assert ok.all(), np.nonzero(~ok)[0]
