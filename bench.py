@@ -36,12 +36,12 @@ FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
 # of ``bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame
 # --copy-calibration 256``.  In those runs a plain 256 MiB device copy read
-# FETCH_SIZE = 131,089 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is scaled
+# FETCH_SIZE = 131,093 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is scaled
 # by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel sources it
 # was taken on (hash below); otherwise the bench reports null.
 KERNEL_SOURCES = ("fofse_group.hip", "iterate.hpp", "device_common.hpp", "fofse_kernel.h")
-TRAFFIC = {"sources_sha256_16": "f5371304433aa6eb", "blocks": 12864,
-           "fetch_kib": 84137.5, "write_kib": 64393.3, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "7457167c8f3ae5d3", "blocks": 12864,
+           "fetch_kib": 84104.6, "write_kib": 64394.2, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def measured_traffic(n_blocks: int):
@@ -87,11 +87,22 @@ def _frame4k(i):
     return a.areas, a.known, a.target, a.truth
 
 
+def _map(fn, items, jobs):
+    """fn over items in a fork pool of ``jobs`` processes (in this process
+    when jobs <= 1, e.g. under a profiler)."""
+    if jobs <= 1:
+        return [fn(x) for x in items]
+    with mp.get_context("fork").Pool(min(jobs, len(items))) as pool:
+        return pool.map(fn, items)
+
+
+JOBS = 16
+
+
 def make_tuning_workload(n_train: int, n_held: int):
     """3840 x 2160 frames with 5 % of the 16 x 16 blocks lost (1,620 per
     frame): n_train frames for the fit, n_held further frames for the PSNR."""
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        parts = pool.map(_frame4k, range(n_train + n_held))
+    parts = _map(_frame4k, range(n_train + n_held), JOBS)
     cat = lambda j, sl: np.concatenate([p[j] for p in parts[sl]])
     tr = slice(0, n_train)
     he = slice(n_train, n_train + n_held)
@@ -108,8 +119,7 @@ def make_mixed_workload(per_class: int, n_frames: int = 4):
     16x16, 32x32 losses), at seeded positions of n_frames synthetic 1080p
     frames, in a seeded order within each class."""
     from paper_2207_01205_amd import synth
-    with mp.get_context("fork").Pool(min(16, n_frames)) as pool:
-        imgs = pool.map(_frame_img, range(n_frames))
+    imgs = _map(_frame_img, range(n_frames), JOBS)
     classes = []
     for ci, (block, support, Tc, Kc) in enumerate(synth.MIXED_CLASSES):
         parts = [synth.mixed_blocks(img, 1000 * ci + j, block, support, per_class // n_frames)
@@ -122,8 +132,7 @@ def make_mixed_workload(per_class: int, n_frames: int = 4):
 
 
 def make_workload(n_frames: int):
-    with mp.get_context("fork").Pool(min(16, n_frames, os.cpu_count() or 1)) as pool:
-        parts = pool.map(_frame, range(n_frames))
+    parts = _map(_frame, range(n_frames), JOBS)
     areas = np.concatenate([p[0] for p in parts])
     known = np.concatenate([p[1] for p in parts])
     truth = np.concatenate([p[3] for p in parts])
@@ -230,6 +239,7 @@ def run_mixed(classes, refs, args, dev):
                      torch.empty((n, c["K"], 2), dtype=torch.float64, device=dev)))
         sts.append(torch.empty((n,), dtype=torch.int32, device=dev))
     mb = MixedBatch(plans)
+    print("[bench] mixed batch: plain, autotune, batched", file=sys.stderr, flush=True)
     n_all = sum(int(x[0].shape[0]) for x in inputs)
     flops = sum(int(x[0].shape[0]) * flops_per_block(c["T"], c["K"]) for x, c in zip(inputs, classes))
     steps = max(3, args.steps // 4)
@@ -387,6 +397,8 @@ def main():
                          "3840x2160 frames with 5%% block loss, one captured graph per step "
                          "(forward, MSE gradient, adjoint), and report held-out PSNR")
     ap.add_argument("--tune-frames", type=int, default=64)
+    ap.add_argument("--jobs", type=int, default=16,
+                    help="processes generating the synthetic inputs (1: in this process)")
     ap.add_argument("--tune-lr", type=float, default=0.1)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, copy MIB MiB once with a plain device copy, so "
@@ -403,8 +415,13 @@ def main():
         sys.exit(2)
 
     # everything that forks runs before the GPU is initialised
+    global JOBS
+    JOBS = args.jobs
+    print(f"[bench] generating {args.frames} frames", file=sys.stderr, flush=True)
     areas, known, target, truth = make_workload(args.frames)
     tune_data = make_tuning_workload(args.tune_frames, 8) if args.tune > 0 else None
+    if args.mixed > 0:
+        print(f"[bench] generating the mixed-size batch", file=sys.stderr, flush=True)
     mixed_data = make_mixed_workload(args.mixed) if args.mixed > 0 else None
     mixed_ref = None
     if mixed_data is not None and not args.no_cpu_baseline:
