@@ -20,6 +20,8 @@ struct fofse_plan_s {
     int M = 0, N = 0, T = 0, K = 0, nB = 0;
     uint8_t* d_target = nullptr;
     int32_t* d_bpix = nullptr;
+    int32_t* d_bidx = nullptr;      // [M*N] index in the B list, -1 off B
+    int b_m0 = 0, b_n0 = 0, b_h = 0, b_w = 0;
     double2* d_twiddle = nullptr;
     double* d_wtab = nullptr;       // rho_hat ** dist per sample, refreshed per call
     double* d_dwtab = nullptr;      // its derivative in rho_hat (adjoint only)
@@ -83,6 +85,7 @@ void free_plan(fofse_plan p) {
     if (p->d_rec_coef) (void)hipFree(p->d_rec_coef);
     if (p->d_target) (void)hipFree(p->d_target);
     if (p->d_bpix) (void)hipFree(p->d_bpix);
+    if (p->d_bidx) (void)hipFree(p->d_bidx);
     if (p->d_twiddle) (void)hipFree(p->d_twiddle);
     if (p->d_wtab) (void)hipFree(p->d_wtab);
     if (p->d_dwtab) (void)hipFree(p->d_dwtab);
@@ -175,6 +178,14 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     if (bpix.empty()) return FOFSE_ERR_ARG;
     if ((int)bpix.size() > fofse::max_target_samples(T)) return FOFSE_ERR_UNSUPPORTED;
 
+    std::vector<int32_t> bidx(M * N, -1);
+    int m0 = M, m1 = -1, n0 = N, n1 = -1;
+    for (size_t q = 0; q < bpix.size(); ++q) {
+        const int i = bpix[q], m = i / N, n = i % N;
+        bidx[i] = (int32_t)q;
+        m0 = m < m0 ? m : m0; m1 = m > m1 ? m : m1;
+        n0 = n < n0 ? n : n0; n1 = n > n1 ? n : n1;
+    }
     std::vector<uint8_t> target(M * N);
     for (int i = 0; i < M * N; ++i) target[i] = g->target_mask[i] ? 1 : 0;
     std::vector<double2> tw(T);
@@ -194,8 +205,10 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     p->n_cu = n_cu;
     p->M = M; p->N = N; p->T = T; p->K = K;
     p->nB = (int)bpix.size();
+    p->b_m0 = m0; p->b_n0 = n0; p->b_h = m1 - m0 + 1; p->b_w = n1 - n0 + 1;
     if (hipMalloc(&p->d_target, M * N) != hipSuccess ||
         hipMalloc(&p->d_bpix, bpix.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&p->d_bidx, (size_t)M * N * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_twiddle, T * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->d_wtab, (size_t)M * N * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->d_dwtab, (size_t)M * N * sizeof(double)) != hipSuccess) {
@@ -204,6 +217,7 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     }
     if (hipMemcpy(p->d_target, target.data(), M * N, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_bpix, bpix.data(), bpix.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_bidx, bidx.data(), (size_t)M * N * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_twiddle, tw.data(), T * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(p);
         return FOFSE_ERR_DEVICE;
@@ -279,6 +293,8 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
     k.known = d_known;
     k.target = p->d_target;
     k.bpix = p->d_bpix;
+    k.bidx = p->d_bidx;
+    k.b_m0 = p->b_m0; k.b_n0 = p->b_n0; k.b_h = p->b_h; k.b_w = p->b_w;
     k.rho_gamma = d_rho_gamma;
     k.twiddle = p->d_twiddle;
     k.wtab = p->d_wtab;

@@ -234,13 +234,4 @@ hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm
     return launch_synthesis(p, stream);
 }
 
-hipError_t launch_synthesis(const KParams& p, hipStream_t stream) {
-    if (p.T == 64) hipLaunchKernelGGL(k_synthesize<64>, dim3(p.n_blocks), dim3(256), 0, stream, p);
-    else if (p.T == 32) hipLaunchKernelGGL(k_synthesize<32>, dim3(p.n_blocks), dim3(256), 0, stream, p);
-    else if (p.T == 16) hipLaunchKernelGGL(k_synthesize<16>, dim3(p.n_blocks), dim3(256), 0, stream, p);
-    else if (p.T == 128) hipLaunchKernelGGL(k_synthesize<128>, dim3(p.n_blocks), dim3(256), 0, stream, p);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
 }  // namespace fofse

@@ -32,6 +32,8 @@ struct KParams {
     double* coef;            // [n][K][2] coefficient record
     int32_t* status;         // [n] or null
     int waves;               // split path: wavefronts per block (0 = default)
+    const int32_t* bidx;     // [M*N] index of the sample in B's list, -1 off B
+    int b_m0, b_n0, b_h, b_w; // bounding box of B (first row, first column, rows, columns)
 };
 
 // Wavefronts per block the split path is built for, per FFT size.

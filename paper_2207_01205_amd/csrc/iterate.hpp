@@ -73,7 +73,7 @@ struct RegSpec {
 
 // One wave's share of the K iterations of one block.  The selection record
 // (class key and coefficient of every iteration) goes to p.sel / p.coef; the
-// model on B is synthesised from it by k_synthesize.  ``live`` = false runs the
+// model on B is synthesised from it by the synthesis kernel.  ``live`` = false runs the
 // same barriers without writing (a wave of a missing or flagged block in a
 // workgroup whose waves synchronise every iteration).
 template <int T, int NW, int WI>
@@ -239,64 +239,5 @@ __device__ __forceinline__ void run_wave(RegSpec<WaveRows<T, NW, WI>::S>& R,
     }
 }
 
-
-// eqs. 1, 2: g on the samples of B from the selection record,
-// g = sum over iterations of 2 Re(c phi_{k,l}) (c phi for a self-conjugate class),
-// phi_{k,l}[m, n] = exp(+j 2 pi (k m + l n) / T).  One workgroup per block; the
-// record is staged through LDS in chunks (class indices and the coefficient
-// already doubled for a pair), then every thread sums its samples.
-template <int T>
-__global__ __launch_bounds__(256) void k_synthesize(KParams p) {
-    constexpr int CHUNK = 512;
-    __shared__ double2 tw[T];
-    __shared__ double2 cc[CHUNK];
-    __shared__ int kl[CHUNK];
-    const int b = (int)__builtin_amdgcn_workgroup_id_x(), tid = (int)__builtin_amdgcn_workitem_id_x();
-    for (int i = tid; i < T; i += 256) tw[i] = p.twiddle[i];
-    const int K = p.K, N = p.N, H = T / 2;
-    const int32_t* sel = p.sel + (size_t)b * K;
-    const double2* coef = (const double2*)(p.coef + 2 * (size_t)b * K);
-    constexpr int PPT = 4;                       // samples per thread and pass
-    for (int q0 = 0; q0 < p.nB; q0 += 256 * PPT) {
-        int mm[PPT], nn[PPT];
-        double g[PPT];
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int q = q0 + tid + 256 * j;
-            const int flat = q < p.nB ? p.bpix[q] : 0;
-            mm[j] = flat / N;
-            nn[j] = flat - mm[j] * N;
-            g[j] = 0.0;
-        }
-        for (int it0 = 0; it0 < K; it0 += CHUNK) {
-            const int cnt = min(CHUNK, K - it0);
-            __syncthreads();
-            for (int i = tid; i < cnt; i += 256) {
-                const int key = sel[it0 + i];
-                const int k = key / T, l = key - k * T;
-                const bool selfc = (k == 0 || k == H) && (l == 0 || l == H);
-                const double2 c = coef[it0 + i];
-                const double mult = selfc ? 1.0 : 2.0;
-                cc[i] = make_double2(mult * c.x, mult * c.y);
-                kl[i] = (k << 16) | l;
-            }
-            __syncthreads();
-            for (int i = 0; i < cnt; ++i) {
-                const int k = kl[i] >> 16, l = kl[i] & 0xFFFF;
-                const double2 c = cc[i];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const double2 t = tw[(k * mm[j] + l * nn[j]) & (T - 1)];   // exp(-j ...)
-                    g[j] = fma(c.x, t.x, fma(c.y, t.y, g[j]));                 // Re(c conj(t))
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int q = q0 + tid + 256 * j;
-            if (q < p.nB) p.out[(size_t)b * p.nB + q] = (float)g[j];
-        }
-    }
-}
 
 }  // namespace fofse
