@@ -80,15 +80,18 @@ fofse_status fofse_create(const fofse_geometry* geometry, int32_t device,
 int32_t fofse_target_count(fofse_plan plan);
 
 /*
- * Kernel organisation used by fofse_extrapolate_batch (results are the same
- * up to rounding of the shared transform; each path is deterministic):
+ * Kernel organisation used by fofse_extrapolate_batch and fofse_backward
+ * (results are the same up to rounding of the shared transform; each path is
+ * deterministic):
  *   FOFSE_PATH_AUTO    (default) grouped when supported and the batch holds at
  *                      least 8 blocks per compute unit, split otherwise;
  *   FOFSE_PATH_SPLIT   one workgroup per block, the block's rows spread over
  *                      several wavefronts (lowest latency for few blocks);
  *   FOFSE_PATH_GROUPED blocks with identical support masks grouped on the device;
  *                      one wavefront per block, one shared W per workgroup
- *                      (highest throughput).  Needs fft_size 64.
+ *                      (highest throughput).  Needs fft_size 64; the
+ *                      adjoint takes it for K <= 256 (one workgroup per block
+ *                      above that).
  * Returns FOFSE_ERR_ARG for a NULL plan or unknown path, FOFSE_ERR_UNSUPPORTED
  * if the grouped path cannot run this geometry.
  */
@@ -201,11 +204,20 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  *
  * Blocks whose forward status would be non-zero (non-finite known sample,
  * W0 <= 0, rho_hat or gamma out of range) get zero gradients.
+ *
+ * The plan's path (fofse_set_path) applies as in the forward: the grouped
+ * adjoint (T = 64 and K <= 256) shares W and its rho_hat derivative between
+ * the blocks of one support mask and runs one wavefront per block; otherwise
+ * one workgroup per block.  Both give the same gradients up to the order of
+ * FP64 rounding, and each is deterministic: the same inputs give the same bits,
+ * whatever other blocks share the batch.
+ *
  * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
  * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
- * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, FOFSE_ERR_NOMEM if the per-block
- * workspace (16 B per block, used when d_grad_block is NULL) cannot be
- * allocated, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
+ * FOFSE_ERR_UNSUPPORTED when K exceeds 2048 or T exceeds 64, FOFSE_ERR_NOMEM if
+ * the per-block workspace (16 B per block, used when d_grad_block is NULL) or
+ * the grouped path's workspace cannot be allocated, FOFSE_ERR_DEVICE if a
+ * launch fails, FOFSE_OK otherwise.
  * n_blocks == 0 is a no-op (d_grad_rho_gamma is not written).
  */
 fofse_status fofse_backward(fofse_plan plan, int32_t n_blocks,

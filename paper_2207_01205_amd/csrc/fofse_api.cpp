@@ -385,6 +385,8 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     b.grad_out = d_grad_out;
     b.grad_areas = d_grad_areas;
     b.grad_block = blk;
+    b.bidx = p->d_bidx;
+    b.b_m0 = p->b_m0; b.b_n0 = p->b_n0; b.b_h = p->b_h; b.b_w = p->b_w;
     fofse::Timing tm{};
     if (p->timing) {
         const int i = (int)(p->n_timed % kRing);
@@ -392,7 +394,29 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         tm.stop = p->ev_stop[i];
         ++p->n_timed;
     }
-    const hipError_t e = fofse::launch_backward(wp, b, d_grad_rho_gamma, (hipStream_t)stream, tm);
+    hipStream_t st = (hipStream_t)stream;
+    // grouped adjoint: same rule as the forward, for K up to its register capacity
+    const bool grouped_ok = grouped_supported(p) && p->K <= fofse::kGroupBackwardMaxK;
+    bool grouped = false;
+    if (p->path == FOFSE_PATH_GROUPED) grouped = grouped_ok;
+    else if (p->path == FOFSE_PATH_AUTO) grouped = grouped_ok && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu;
+    hipError_t e;
+    if (grouped) {
+        fofse::GroupArgs g{};
+        g.MN = p->M * p->N;
+        g.known = d_known;
+        g.target = p->d_target;
+        g.direct = d_known == nullptr;
+        if (!g.direct) {
+            const fofse_status ws = ensure_workspace(p, n_blocks, g);
+            if (ws != FOFSE_OK) return ws;
+            e = fofse::launch_clear(g, st);
+            if (e != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        e = fofse::launch_backward_grouped(wp, b, g, p->n_cu, d_grad_rho_gamma, st, tm);
+    } else {
+        e = fofse::launch_backward(wp, b, d_grad_rho_gamma, st, tm);
+    }
     return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
 }
 

@@ -26,85 +26,23 @@
 // with D = DFT(dw/drho): the derivative through W never forms the adjoint
 // spectrum of W, it pairs each of its K(K-1) entries with D directly.
 //
-// One workgroup per block.  W and D come from one complex FFT of
-// z = w + j dw/drho in LDS (separated by Hermitian symmetry at each read); the
-// recurrence runs in panels of 64 iterations: one wavefront resolves a panel
-// serially (lane = iteration, the finished adjoint is broadcast with
-// readlane), then all waves apply the panel to the earlier iterations and
-// accumulate the rho terms.  (w f)bar comes from one more 2-D FFT.
+// One workgroup per block (the grouped adjoint in fofse_bwd_group.hip serves
+// batches of blocks that share support masks).  W and D come from one complex
+// FFT of z = w + j dw/drho in LDS (separated by Hermitian symmetry at each
+// read); the recurrence runs in panels of 16 iterations: one wavefront
+// resolves a panel serially (lane = iteration, the finished adjoint is
+// broadcast with readlane) while the other waves apply the previous panel to
+// the earlier iterations and accumulate the rho terms.  (w f)bar comes from
+// one more 2-D FFT.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "fofse_kernel.h"
 #include "device_common.hpp"
+#include "adjoint.hpp"
 
 namespace fofse {
-
-namespace {
-
-// grid index of frequency (k, l), natural order and FFT output order
-template <int T>
-__device__ __forceinline__ int zi(int k, int l) {
-    return ((k & (T - 1)) * T) | (l & (T - 1));
-}
-template <int T>
-__device__ __forceinline__ int zp(int k, int l) {
-    return FftPlan<T>::perm(k & (T - 1)) * T + FftPlan<T>::perm(l & (T - 1));
-}
-
-template <int T>
-struct Key {
-    static constexpr int LOG2 = T == 128 ? 7 : T == 64 ? 6 : T == 32 ? 5 : 4;
-    __device__ static int k(int key) { return (key >> LOG2) & (T - 1); }
-    __device__ static int l(int key) { return key & (T - 1); }
-    __device__ static bool pair(int k, int l) {
-        return !(((k & (T / 2 - 1)) == 0) && ((l & (T / 2 - 1)) == 0));
-    }
-};
-
-// Byte offsets of Z[u_j - u_i], Z[u_i - u_j], Z[u_j + u_i], Z[-u_j - u_i] in the
-// LDS spectrum, for a per-lane class u_i = (ku, lu) and a uniform u_j.
-// T = 64: Z in natural order; the two indices travel packed as k << 8 | l with
-// a guard bit (128) that keeps the l field from borrowing, so each offset is
-// one add or subtract and three bit operations.  Other T: FFT output order.
-template <int T>
-struct ZOff {
-    int ku, lu;
-    __device__ ZOff(int k, int l) : ku(k), lu(l) {}
-    __device__ void get(int kj, int lj, int& a, int& b, int& c, int& d) const {
-        a = 16 * zp<T>(kj - ku, lj - lu);
-        b = 16 * zp<T>(ku - kj, lu - lj);
-        c = 16 * zp<T>(kj + ku, lj + lu);
-        d = 16 * zp<T>(-kj - ku, -lj - lu);
-    }
-};
-
-template <>
-struct ZOff<64> {
-    int yd, ym;
-    __device__ ZOff(int k, int l) : yd((k << 8) | l), ym((k << 8) | 128 | l) {}
-    __device__ static int off(int r) { return ((r << 2) & 0xFC00) | ((r << 4) & 0x3F0); }
-    __device__ void get(int kj, int lj, int& a, int& b, int& c, int& d) const {
-        const int xs = (kj << 8) | lj;
-        a = off((xs | 128) - yd);
-        b = off(ym - xs);
-        c = off(xs + yd);
-        d = off(((64 << 8) | 128) - xs - yd);
-    }
-};
-
-__device__ __forceinline__ double2 lds_at(const double2* base, int byte_off) {
-    return *(const double2*)((const char*)base + byte_off);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-}  // namespace
 
 template <int T, int KMAX>
 __global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BParams p) {
@@ -561,12 +499,13 @@ hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, h
     else e = p.K <= 256 ? launch_bwd<16, 256>(p, stream) : launch_bwd<16, kBackwardMaxK>(p, stream);
     if (e != hipSuccess) return e;
     if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
-    if (d_sum) {
-        hipLaunchKernelGGL(k_bwd_sum, dim3(1), dim3(256), 0, stream, (const double*)p.grad_block,
-                           p.n_blocks, d_sum);
-        e = hipGetLastError();
-    }
-    return e;
+    return d_sum ? launch_bwd_sum(p, d_sum, stream) : hipSuccess;
+}
+
+hipError_t launch_bwd_sum(const BParams& p, double* d_sum, hipStream_t stream) {
+    hipLaunchKernelGGL(k_bwd_sum, dim3(1), dim3(256), 0, stream, (const double*)p.grad_block, p.n_blocks,
+                       d_sum);
+    return hipGetLastError();
 }
 
 }  // namespace fofse

@@ -1,0 +1,485 @@
+// Grouped adjoint of the FOFSE forward pass for gfx950 (T = 64, K <= 256).
+//
+// The arithmetic is the transposed recurrence of the per-block adjoint
+// (fofse_bwd.hip states it in full): with the selection record fixed,
+//   cbar_nu = mult Gbar[u_nu]
+//             - sum_{mu>nu} (sbar_mu conj(W[u_mu - u_nu]) + conj(sbar_mu) W[u_mu + u_nu])
+//   sbar_nu = gamma / W0 cbar_nu       (real part for a self-conjugate class)
+// plus the rho terms, which pair sbar with D = DFT(dw/drho), and one inverse
+// transform of Rbar0 for dL/df (eqs. 1-5, 7, 8, 14, 15).
+//
+// Blocks whose support areas have the same known-sample mask share w, hence W
+// and D (eqs. 4 and 15 depend on the mask only).  A workgroup takes the work
+// items of the grouped forward (up to kGroup blocks of one mask), builds
+// Z = W + j D once in LDS and gives each block one wavefront:
+//   * the K iterations of a block live in registers, K / 64 per lane (row
+//     mu = lane + 64 r) with class, coefficient and running adjoint;
+//   * rows are resolved from the last chunk of 64 down: inside a chunk
+//     serially (the finished adjoint of row j is broadcast with readlane and
+//     applied to the rows below it), then the whole chunk is applied to every
+//     lower chunk with all lanes busy;
+//   * Gbar[u_nu] is separable over the rows of B's bounding box;
+//   * Rbar0 is scattered, made Hermitian, so that its transform is real; the
+//     even and odd columns of that real result come from one 64 x 32 complex
+//     FFT per block (two blocks per 64 KB pass).  The scatter adds in 64-bit
+//     fixed point (exact integer sums at a resolution of 2^-49 of the block's
+//     largest value), so the result does not depend on the order in which the
+//     atomic adds land, nor on the other blocks of the work item.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adjoint.hpp"
+#include "device_common.hpp"
+#include "fofse_kernel.h"
+
+namespace fofse {
+
+namespace {
+
+constexpr int kRC = kGroupBackwardMaxK / 64;   // row chunks per lane
+constexpr int kZeroOff = 64 * 64 * 16;         // byte offset of the zero entry after Z
+
+__device__ __forceinline__ bool known_at(const uint8_t* known, const uint8_t* target, size_t base, int i) {
+    return target[i] == 0 && (known == nullptr || known[base + i] != 0);
+}
+
+// class packed as k << 8 | l: self-conjugate when k and l are 0 or 32
+__device__ __forceinline__ bool packed_pair(int x) { return (x & 0x1F1F) != 0; }
+
+// exact power of two, -1022 <= n <= 1023
+__device__ __forceinline__ double pow2(int n) { return __hiloint2double((n + 1023) << 20, 0); }
+
+// The four samples of Z' a pair of classes needs: Z'[u_nu - u_mu],
+// Z'[u_mu - u_nu], Z'[u_nu + u_mu], Z'[-u_nu - u_mu] for the packed classes xs
+// (uniform, nu) and yd (per lane, mu); the last two read the zero entry when mu
+// is self-conjugate (it takes one term only).
+struct ZQ {
+    double2 a, b, c, d;
+};
+
+__device__ __forceinline__ ZQ zgather(const double2* Z, int xs, int yd, bool pr) {
+    using ZO = ZOff<64>;
+    const int oa = ZO::off((xs | 128) - yd);
+    const int ob = ZO::off((yd | 128) - xs);
+    const int oc = pr ? ZO::off(xs + yd) : kZeroOff;
+    const int od = pr ? ZO::off(((64 << 8) | 128) - xs - yd) : kZeroOff;
+    ZQ q;
+    q.a = lds_at(Z, oa);
+    q.b = lds_at(Z, ob);
+    q.c = lds_at(Z, oc);
+    q.d = lds_at(Z, od);
+    return q;
+}
+
+// Row mu takes the finished iteration nu.  Z' = gamma / (2 W0) Z, so with
+// (sr, si) = cbar_nu and 2 W[d] = Z[d] + conj Z[-d], 2 j D[d] = Z[d] - conj Z[-d]:
+//   cbar_mu -= sbar conj(W[u_nu - u_mu]) + conj(sbar) W[u_nu + u_mu]
+//   racc    -= Re(sbar conj(c_mu D[u_nu - u_mu])) + Re(sbar conj(conj(c_mu) D[u_nu + u_mu]))
+__device__ __forceinline__ void zapply(const ZQ& q, double sr, double si, double2 c, double2& cb,
+                                       double& rr) {
+    const double s1 = q.a.x + q.b.x, s2 = q.c.x + q.d.x;   // Re W[d], Re W[s] (scaled)
+    const double d1 = q.a.y - q.b.y, d2 = q.c.y - q.d.y;   // Im W
+    const double e1 = q.a.y + q.b.y, e2 = q.c.y + q.d.y;   // Re D
+    const double f1 = q.b.x - q.a.x, f2 = q.d.x - q.c.x;   // Im D
+    cb.x -= sr * (s1 + s2) + si * (d1 + d2);
+    cb.y -= si * (s1 - s2) - sr * (d1 - d2);
+    const double qr = c.x * (e1 + e2) - c.y * (f1 - f2);
+    const double qi = c.x * (f1 + f2) + c.y * (e1 - e2);
+    rr -= sr * qr + si * qi;
+}
+
+// The iterations of one block, row mu = lane + 64 r.
+struct Rows {
+    int yd[kRC];       // class, packed k << 8 | l
+    bool pr[kRC];      // not self-conjugate (and a valid row)
+    double2 c[kRC];    // forward coefficient c_mu
+    double2 cb[kRC];   // cbar_mu: running, then final
+};
+
+struct BwdGroupShared {
+    double2 buf[64 * 64 + 1];   // H tables, then Z', then the output grids; + zero entry
+    double2 tw[64];             // exp(-j 2 pi q / 64)
+    double2 tw32[32];           // exp(-j 2 pi q / 32)
+    int expo[kGroup];
+};
+
+// Serial sweep of chunk r: row j (from the last) is final when reached; it is
+// applied to the rows below it in the chunk.  The samples of the next step are
+// gathered before the current step is computed.
+template <int r>
+__device__ __forceinline__ void sweep_chunk(Rows& R, const double2* Z, int lane, int nv, double& rr) {
+    auto step = [&](int j, int x, const ZQ& q) {
+        const double cr = readlane_f64(R.cb[r].x, j);
+        const double ci = packed_pair(x) ? readlane_f64(R.cb[r].y, j) : 0.0;
+        if (lane < j) zapply(q, cr, ci, R.c[r], R.cb[r], rr);
+    };
+    int j = nv - 1;
+    int xa = __builtin_amdgcn_readlane(R.yd[r], j);
+    ZQ qa = zgather(Z, xa, R.yd[r], R.pr[r]);
+    for (; j >= 1; j -= 2) {
+        const int xb = __builtin_amdgcn_readlane(R.yd[r], j - 1);
+        const ZQ qb = zgather(Z, xb, R.yd[r], R.pr[r]);
+        step(j, xa, qa);
+        xa = __builtin_amdgcn_readlane(R.yd[r], max(j - 2, 0));
+        qa = zgather(Z, xa, R.yd[r], R.pr[r]);
+        step(j - 1, xb, qb);
+    }
+    if (j == 0) step(0, xa, qa);
+    if (!R.pr[r]) R.cb[r].y = 0.0;        // final adjoint of a self-conjugate class is real
+}
+
+// The finished chunk r applied to every lower chunk (all lanes, all rows valid).
+template <int r>
+__device__ __forceinline__ void cross_chunk(Rows& R, const double2* Z, int nv, double& rr) {
+    for (int j = 0; j < nv; ++j) {
+        const int x = __builtin_amdgcn_readlane(R.yd[r], j);
+        const double cr = readlane_f64(R.cb[r].x, j);
+        const double ci = readlane_f64(R.cb[r].y, j);
+#pragma unroll
+        for (int r2 = 0; r2 < r; ++r2) {
+            const ZQ q = zgather(Z, x, R.yd[r2], R.pr[r2]);
+            zapply(q, cr, ci, R.c[r2], R.cb[r2], rr);
+        }
+    }
+}
+
+template <int r>
+__device__ __forceinline__ void chunk(Rows& R, const double2* Z, int lane, int K, double& rr) {
+    const int nv = min(64, K - 64 * r);
+    if (nv > 0) {
+        sweep_chunk<r>(R, Z, lane, nv, rr);
+        if constexpr (r > 0) cross_chunk<r>(R, Z, nv, rr);
+    }
+}
+
+// cbar0_nu = mult Gbar[u_nu] with Gbar[k, l] = sum_B gbar[m, n] exp(-j 2 pi (k m + l n) / 64),
+// separable over the rows of B's bounding box: H[m][l] = sum_n gbar[m, n] tw[l n]
+// (lane = l, 16 box rows per pass, in this wave's 16 KB of LDS), then
+// Gbar[k, l] = sum_m tw[k m] H[m][l] (lane = iteration).
+__device__ __forceinline__ void cbar0_rows(const BParams& p, int bj, int lane, double2* H,
+                                           const double2* tw, Rows& R, int K) {
+    double2 acc[kRC];
+#pragma unroll
+    for (int r = 0; r < kRC; ++r) acc[r] = make_double2(0.0, 0.0);
+    const int N = p.N;
+    const float* go = p.grad_out + (size_t)bj * p.nB;
+    for (int m0 = 0; m0 < p.b_h; m0 += 16) {
+        float gv[16];
+        const int n = p.b_n0 + lane;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            gv[i] = 0.0f;
+            if (lane < p.b_w && m0 + i < p.b_h) {
+                const int q = p.bidx[(p.b_m0 + m0 + i) * N + n];
+                if (q >= 0) gv[i] = go[q];
+            }
+        }
+        double2 h[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) h[i] = make_double2(0.0, 0.0);
+        for (int c = 0; c < p.b_w; ++c) {
+            const double2 t = tw[(lane * (p.b_n0 + c)) & 63];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double g = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[i]), c));
+                h[i].x = fma(g, t.x, h[i].x);
+                h[i].y = fma(g, t.y, h[i].y);
+            }
+        }
+        // this wavefront's LDS rows: its lanes see each other's writes in program order
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) H[i * 64 + lane] = h[i];
+        __builtin_amdgcn_wave_barrier();
+        const int rows = min(16, p.b_h - m0);
+#pragma unroll
+        for (int r = 0; r < kRC; ++r) {
+            const int k = R.yd[r] >> 8, l = R.yd[r] & 63;
+            for (int i = 0; i < rows; ++i) {
+                const double2 hv = H[i * 64 + l];
+                const double2 t = tw[(k * (p.b_m0 + m0 + i)) & 63];
+                acc[r].x += hv.x * t.x - hv.y * t.y;
+                acc[r].y += hv.x * t.y + hv.y * t.x;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int r = 0; r < kRC; ++r) {
+        const bool valid = lane + 64 * r < K;
+        const bool sc = !packed_pair(R.yd[r]);
+        R.cb[r] = !valid ? make_double2(0.0, 0.0)
+                         : sc ? make_double2(acc[r].x, 0.0) : make_double2(2.0 * acc[r].x, 2.0 * acc[r].y);
+    }
+}
+
+}  // namespace
+
+template <int MAXPX>
+__global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams p, GroupArgs g) {
+    constexpr int T = 64, NT = 64 * kGroup;
+    __shared__ BwdGroupShared sh;
+
+    const int tid = (int)__builtin_amdgcn_workitem_id_x(), lane = tid & 63, wave = tid >> 6;
+    const int M = p.M, N = p.N, MN = M * N, K = p.K;
+    const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
+    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
+    for (int i = tid; i < 32; i += NT) sh.tw32[i] = p.twiddle[2 * i];
+    if (tid == 0) sh.buf[T * T] = make_double2(0.0, 0.0);
+
+    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
+    const int per = (n_items + g.n_wg - 1) / g.n_wg;
+    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+    const int i1 = min(n_items, i0 + per);
+
+    for (int item = i0; item < i1; ++item) {
+        int nblk, b0, b1, b2, b3;
+        if (g.direct) {
+            nblk = min(kGroup, p.n_blocks - item * kGroup);
+            b0 = item * kGroup;
+            b1 = b0 + 1;
+            b2 = b0 + 2;
+            b3 = b0 + 3;
+        } else {
+            const int* ib = g.item_blk + (size_t)item * kGroup;
+            nblk = g.item_n[item];
+            b0 = ib[0];
+            b1 = ib[1];
+            b2 = ib[2];
+            b3 = ib[3];
+        }
+        static_assert(kGroup == 4, "one wavefront per block slot");
+        const int b_rep = b0;                    // every block of the item has this mask
+        const bool present = wave < nblk;
+        const int bj = present ? __builtin_amdgcn_readfirstlane(wave == 0 ? b0 : wave == 1 ? b1 : wave == 2 ? b2 : b3)
+                               : 0;
+        const size_t ab = (size_t)bj * MN;
+        // thread index as an opaque per-item value: keeps the compiler from
+        // hoisting every per-thread address of the item's loops out of the
+        // item loop (they would pin registers for the whole kernel)
+        int tidv = tid;
+        asm volatile("" : "+v"(tidv));
+        __syncthreads();                         // previous item done with LDS
+
+        // per wavefront: flags, record, cbar0
+        int flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+        if (present) {
+            bool bad = false;
+            for (int i = lane; i < MN; i += 64)
+                if (known_at(p.known, p.target, ab, i)) {
+                    const float x = p.areas[ab + i];
+                    bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
+                }
+            if (__any(bad)) flags |= FOFSE_BLOCK_NONFINITE;
+        }
+        Rows R;
+#pragma unroll
+        for (int r = 0; r < kRC; ++r) {
+            const int nu = lane + 64 * r;
+            const bool valid = present && nu < K;
+            int key = 0;
+            double2 c = make_double2(0.0, 0.0);
+            if (valid) {
+                key = p.sel[(size_t)bj * K + nu] & (T * T - 1);
+                c = make_double2(p.coef[2 * ((size_t)bj * K + nu)], p.coef[2 * ((size_t)bj * K + nu) + 1]);
+            }
+            R.yd[r] = ((key >> 6) << 8) | (key & 63);
+            R.pr[r] = valid && packed_pair(R.yd[r]);
+            R.c[r] = c;
+            R.cb[r] = make_double2(0.0, 0.0);
+        }
+        if (present && flags == 0) cbar0_rows(p, bj, lane, sh.buf + wave * 1024, sh.tw, R, K);
+        __syncthreads();                         // H tables done
+
+        // Z = DFT(w + j dw/drho) of the item's mask, natural order
+        for (int i = tidv; i < T * T; i += NT) sh.buf[i] = make_double2(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q) {
+            const int i = tidv + q * NT;
+            if (i < MN && known_at(p.known, p.target, (size_t)b_rep * MN, i)) {
+                const int m = i / N, n = i - m * N;
+                sh.buf[m * T + n] = make_double2(p.wtab[i], p.dwtab[i]);
+            }
+        }
+        __syncthreads();
+        fft_stage_a<T, NT>(sh.buf, sh.tw, M, T, 1, tidv);
+        __syncthreads();
+        fft_stage_b<T, NT>(sh.buf, M, T, 1, tidv);
+        __syncthreads();
+        fft_stage_a<T, NT>(sh.buf, sh.tw, T, 1, T, tidv);
+        __syncthreads();
+        fft_stage_b<T, NT>(sh.buf, T, 1, T, tidv);
+        __syncthreads();
+        // FFT output order -> natural order: for T = 64 the order swaps the two
+        // octal digits of each index, an involution
+        for (int e = tidv; e < T * T; e += NT) {
+            const int pe = FftPlan<T>::perm(e / T) * T + FftPlan<T>::perm(e % T);
+            if (pe > e) {
+                const double2 x = sh.buf[e], y = sh.buf[pe];
+                sh.buf[e] = y;
+                sh.buf[pe] = x;
+            }
+        }
+        __syncthreads();
+        const double W0 = sh.buf[0].x, dW0 = sh.buf[0].y;
+        __syncthreads();
+        if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
+        const bool live = present && flags == 0;
+        const double hW = (params_ok && W0 > 0.0) ? 0.5 * gamma / W0 : 0.0;
+        for (int i = tidv; i < T * T; i += NT) {
+            const double2 z = sh.buf[i];
+            sh.buf[i] = make_double2(hW * z.x, hW * z.y);
+        }
+        __syncthreads();
+
+        // the transposed recurrence of this wavefront's block
+        double racc = 0.0, tacc = 0.0;
+        if (live) {
+            chunk<3>(R, sh.buf, lane, K, racc);
+            chunk<2>(R, sh.buf, lane, K, racc);
+            chunk<1>(R, sh.buf, lane, K, racc);
+            chunk<0>(R, sh.buf, lane, K, racc);
+#pragma unroll
+            for (int r = 0; r < kRC; ++r)
+                if (lane + 64 * r < K) tacc += R.cb[r].x * R.c[r].x + R.cb[r].y * R.c[r].y;
+        }
+
+        // (w f)bar = Re FFT(Y), Y = conj(gamma / W0 cbar) summed per class.  Made
+        // Hermitian, Yh = (Y(k) + conj Y(-k)) / 2, its transform x is real, and the
+        // even and odd columns of x travel as one 64 x 32 complex transform:
+        //   z[m][n'] = x[m][2n'] + j x[m][2n'+1] = FFT(C)[m][n'],
+        //   C[k][l'] = Yh[k][l'] + Yh[k][l'+32] + j (Yh[k][l'] - Yh[k][l'+32]) w^l'
+        // (w = exp(-j 2 pi / 64)).  Each block has its own 32 KB grid (two blocks
+        // per pass) and its own fixed-point scale, so its result does not depend on
+        // the other blocks of the work item.
+        const double gW = 2.0 * hW;
+        unsigned long long* acc = (unsigned long long*)sh.buf;
+        for (int pp = 0; pp < 2; ++pp) {
+            if (2 * pp >= nblk) break;           // uniform over the workgroup
+            const bool mine = (wave >> 1) == pp;
+            const int grid = wave & 1;
+            __syncthreads();                     // Z' or the previous grids no longer read
+            for (int i = tidv; i < 2 * T * T; i += NT) acc[i] = 0ull;
+            if (mine) {
+                uint32_t eb = 0;
+                if (live) {
+#pragma unroll
+                    for (int r = 0; r < kRC; ++r)
+                        if (lane + 64 * r < K) {
+                            const uint32_t ex = (uint32_t)(__double2hiint(gW * R.cb[r].x) >> 20) & 0x7FF;
+                            const uint32_t ey = (uint32_t)(__double2hiint(gW * R.cb[r].y) >> 20) & 0x7FF;
+                            eb = max(eb, max(ex, ey));
+                        }
+                }
+                eb = wave_max_u32(eb);
+                // 2^e exceeds every |component| of Y; tiny or empty blocks use -900
+                const int e = max(-900, (int)eb - 1022);
+                if (lane == 0) sh.expo[wave] = e;
+            }
+            __syncthreads();
+            if (mine && live) {
+                // a term Y / 2 (1 +- j w^l') has components below 2^(e + 1): at
+                // S = 2^(49 - e) below 2^50, and at most 4 K <= 2^10 terms meet in an entry
+                const double S = pow2(49 - sh.expo[wave]);
+                unsigned long long* ga = acc + grid * 2 * 2048;
+                auto put = [&](int kk, int ll, double vr, double vi) {
+                    const int lp = ll & 31;
+                    const double2 w = sh.tw[lp];
+                    const double sg = ll < 32 ? 1.0 : -1.0;
+                    const double fr = 1.0 - sg * w.y, fi = sg * w.x;      // 1 +- j w^l'
+                    const long long qr = __double2ll_rn((vr * fr - vi * fi) * S);
+                    const long long qi = __double2ll_rn((vr * fi + vi * fr) * S);
+                    atomicAdd(&ga[2 * (kk * 32 + lp)], (unsigned long long)qr);
+                    atomicAdd(&ga[2 * (kk * 32 + lp) + 1], (unsigned long long)qi);
+                };
+#pragma unroll
+                for (int r = 0; r < kRC; ++r) {
+                    if (lane + 64 * r < K) {
+                        const double yr = 0.5 * gW * R.cb[r].x, yi = -0.5 * gW * R.cb[r].y;
+                        const int k = R.yd[r] >> 8, l = R.yd[r] & 63;
+                        put(k, l, yr, yi);                       // Y / 2 at (k, l)
+                        put((-k) & 63, (-l) & 63, yr, -yi);      // conj(Y) / 2 at (-k, -l)
+                    }
+                }
+            }
+            __syncthreads();
+            for (int i = tidv; i < T * T; i += NT) {
+                const double U = pow2(sh.expo[2 * pp + (i >> 11)] - 49);
+                const long long a = (long long)acc[2 * i], b = (long long)acc[2 * i + 1];
+                sh.buf[i] = make_double2((double)a * U, (double)b * U);
+            }
+            __syncthreads();
+            // 32-point transforms along the rows of both grids, then 64-point
+            // transforms along the columns of each
+            fft_stage_a<32, NT>(sh.buf, sh.tw32, 2 * T, 32, 1, tidv);
+            __syncthreads();
+            fft_stage_b<32, NT>(sh.buf, 2 * T, 32, 1, tidv);
+            __syncthreads();
+            fft_stage_a<T, NT>(sh.buf, sh.tw, 32, 1, 32, tidv);
+            fft_stage_a<T, NT>(sh.buf + 2048, sh.tw, 32, 1, 32, tidv);
+            __syncthreads();
+            fft_stage_b<T, NT>(sh.buf, 32, 1, 32, tidv);
+            fft_stage_b<T, NT>(sh.buf + 2048, 32, 1, 32, tidv);
+            __syncthreads();
+            if (mine && present) {
+                // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f)
+                const double2* zg = sh.buf + grid * 2048;
+                for (int i = lane; i < MN; i += 64) {
+                    float gv = 0.0f;
+                    if (live && known_at(p.known, p.target, ab, i)) {
+                        const int m = i / N, n = i - m * N;
+                        const double2 v = zg[FftPlan<T>::perm(m) * 32 + FftPlan<32>::perm(n >> 1)];
+                        const double wfb = (n & 1) ? v.y : v.x;
+                        gv = (float)(p.wtab[i] * wfb);
+                        racc += p.dwtab[i] * (double)p.areas[ab + i] * wfb;
+                    }
+                    if (p.grad_areas) p.grad_areas[ab + i] = gv;
+                }
+            }
+        }
+        if (present) {
+            racc = wave_sum(racc);
+            tacc = wave_sum(tacc);
+            if (lane == 0) {
+                if (live) {
+                    p.grad_block[2 * bj] = racc - tacc / W0 * dW0;   // W0 = sum w: dW0/drho = sum dw
+                    p.grad_block[2 * bj + 1] = tacc / gamma;
+                } else {
+                    p.grad_block[2 * bj] = 0.0;
+                    p.grad_block[2 * bj + 1] = 0.0;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const GroupArgs& g, int n_cu,
+                                   double* d_sum, hipStream_t stream, const Timing& tm) {
+    if (p.T != 64 || p.K > kGroupBackwardMaxK || p.M * p.N > 16 * 64 * kGroup) return hipErrorInvalidValue;
+    hipError_t e = launch_weights(wp, stream);
+    if (e != hipSuccess) return e;
+    if (!g.direct) {
+        e = launch_grouping(g, p.n_blocks, stream);
+        if (e != hipSuccess) return e;
+    }
+    const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
+    int grid = 2 * n_cu;
+    if (grid > max_items) grid = max_items;
+    GroupArgs ga = g;
+    ga.n_wg = grid;
+    constexpr int NT = 64 * kGroup;
+    if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
+    if (p.M * p.N <= 9 * NT)
+        hipLaunchKernelGGL((fofse_bwd_group_kernel<9>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    else
+        hipLaunchKernelGGL((fofse_bwd_group_kernel<16>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
+    return d_sum ? launch_bwd_sum(p, d_sum, stream) : hipSuccess;
+}
+
+}  // namespace fofse

@@ -380,18 +380,23 @@ hipError_t launch_clear(const GroupArgs& g, hipStream_t stream) {
     return hipGetLastError();
 }
 
+hipError_t launch_grouping(const GroupArgs& g, int n, hipStream_t stream) {
+    const int nwg = (n + kHashBlocks - 1) / kHashBlocks;
+    hipLaunchKernelGGL(k_mask_hash, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
+    hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, stream, g);
+    hipLaunchKernelGGL(k_group_fill, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
                           const Timing& tm) {
     if (p.T != 64) return hipErrorInvalidValue;
     const hipError_t ew = launch_weights(p, stream);
     if (ew != hipSuccess) return ew;
     if (!g.direct) {
-        const int n = p.n_blocks;
-        const int nwg = (n + kHashBlocks - 1) / kHashBlocks;
-        hipLaunchKernelGGL(k_mask_hash, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
-        hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
-        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, stream, g);
-        hipLaunchKernelGGL(k_group_fill, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
+        const hipError_t eg = launch_grouping(g, p.n_blocks, stream);
+        if (eg != hipSuccess) return eg;
     }
     const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
     int grid = 2 * n_cu;

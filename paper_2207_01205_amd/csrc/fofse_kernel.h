@@ -56,6 +56,8 @@ struct BParams {
     const float* grad_out;   // [n][nB] dL/dg on B
     float* grad_areas;       // [n][M*N] dL/df, or null
     double* grad_block;      // [n][2] per-block (dL/drho_hat, dL/dgamma)
+    const int32_t* bidx;     // [M*N] index of the sample in B's list, -1 off B
+    int b_m0, b_n0, b_h, b_w; // bounding box of B
 };
 
 // Largest K the adjoint kernel holds in LDS.
@@ -63,6 +65,9 @@ constexpr int kBackwardMaxK = 2048;
 
 // Blocks per workgroup in the grouped path (they share one W).
 constexpr int kGroup = 4;
+
+// Largest K of the grouped adjoint (K / 64 rows per lane in registers).
+constexpr int kGroupBackwardMaxK = 256;
 
 // Device workspace and arguments of the grouped path.
 struct GroupArgs {
@@ -106,5 +111,10 @@ hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
 hipError_t launch_fwd128(const KParams& p, hipStream_t stream);
 hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
                            const Timing& tm);
+// Mask classes and work items of n blocks (grouped forward and adjoint).
+hipError_t launch_grouping(const GroupArgs& g, int n, hipStream_t stream);
+hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const GroupArgs& g, int n_cu,
+                                   double* d_sum, hipStream_t stream, const Timing& tm);
+hipError_t launch_bwd_sum(const BParams& p, double* d_sum, hipStream_t stream);
 
 }  // namespace fofse
