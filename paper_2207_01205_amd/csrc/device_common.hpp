@@ -178,6 +178,15 @@ __device__ __forceinline__ double sq_add(double a, double c) {
     return r;
 }
 
+// A float sample read as its bit pattern, and the test for an exponent of all
+// ones (Inf or NaN) on those bits.  The library is compiled without NaN
+// semantics; under them the compiler may rewrite a bit test on a float value
+// into |x| == inf, which is false for NaN, so the test never sees a float.
+__device__ __forceinline__ uint32_t sample_bits(const float* a, size_t i) {
+    return reinterpret_cast<const uint32_t*>(a)[i];
+}
+__device__ __forceinline__ bool nonfinite_bits(uint32_t b) { return (b & 0x7f800000u) == 0x7f800000u; }
+
 // 0 < x <= 1, false for NaN (tested on the bits, see the input check).
 __device__ __forceinline__ bool param_ok(double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);

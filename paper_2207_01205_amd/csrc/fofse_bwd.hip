@@ -82,17 +82,17 @@ __global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BPa
     const size_t ab = (size_t)b * MN;
     {
         bool a[PPT];
-        float fv[PPT];
+        uint32_t fb[PPT];
         double w[PPT], dw[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int i = tid + j * NT;
             a[j] = false;
-            fv[j] = 0.0f;
+            fb[j] = 0u;
             w[j] = dw[j] = 0.0;
             if (i < MN) {
                 a[j] = p.target[i] == 0 && (!p.known || p.known[ab + i] != 0);
-                fv[j] = p.areas[ab + i];
+                fb[j] = sample_bits(p.areas, ab + i);
                 w[j] = p.wtab[i];
                 dw[j] = p.dwtab[i];
             }
@@ -103,8 +103,7 @@ __global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BPa
             const int i = tid + j * NT;
             if (i < MN) {
                 const int m = i / N, n = i - m * N;
-                // exponent all ones = Inf or NaN (tested on the bits)
-                const bool nf = (__float_as_uint(fv[j]) & 0x7f800000u) == 0x7f800000u;
+                const bool nf = nonfinite_bits(fb[j]);
                 bad |= a[j] && nf;
                 const bool use = a[j] && !nf;
                 buf[m * T + n] = use ? make_double2(w[j], dw[j]) : make_double2(0.0, 0.0);

@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kRC = kGroupBackwardMaxK / 64;   // row chunks per lane
 constexpr int kZeroOff = 64 * 64 * 16;         // byte offset of the zero entry after Z
+constexpr int kBatch = 6;                      // samples per lane with loads in flight
 
 __device__ __forceinline__ bool known_at(const uint8_t* known, const uint8_t* target, size_t base, int i) {
     return target[i] == 0 && (known == nullptr || known[base + i] != 0);
@@ -102,6 +103,7 @@ struct BwdGroupShared {
     double2 tw[64];             // exp(-j 2 pi q / 64)
     double2 tw32[32];           // exp(-j 2 pi q / 32)
     int expo[kGroup];
+    uint8_t mask[64 * 64];      // support mask of the work item's blocks
 };
 
 // Serial sweep of chunk r: row j (from the last) is final when reached; it is
@@ -262,16 +264,32 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         int tidv = tid;
         asm volatile("" : "+v"(tidv));
         __syncthreads();                         // previous item done with LDS
+        // the item's support mask, once for all its blocks
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q) {
+            const int i = tidv + q * NT;
+            if (i < MN) sh.mask[i] = known_at(p.known, p.target, (size_t)b_rep * MN, i) ? 1 : 0;
+        }
+        __syncthreads();
 
         // per wavefront: flags, record, cbar0
         int flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
         if (present) {
+            // kBatch samples per lane in flight
             bool bad = false;
-            for (int i = lane; i < MN; i += 64)
-                if (known_at(p.known, p.target, ab, i)) {
-                    const float x = p.areas[ab + i];
-                    bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
+            for (int i0 = lane; i0 < MN; i0 += 64 * kBatch) {
+                uint32_t x[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int i = i0 + 64 * u;
+                    x[u] = i < MN ? sample_bits(p.areas, ab + i) : 0u;
                 }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int i = i0 + 64 * u;
+                    if (i < MN && sh.mask[i]) bad |= nonfinite_bits(x[u]);
+                }
+            }
             if (__any(bad)) flags |= FOFSE_BLOCK_NONFINITE;
         }
         Rows R;
@@ -299,7 +317,7 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
 #pragma unroll
         for (int q = 0; q < MAXPX; ++q) {
             const int i = tidv + q * NT;
-            if (i < MN && known_at(p.known, p.target, (size_t)b_rep * MN, i)) {
+            if (i < MN && sh.mask[i]) {
                 const int m = i / N, n = i - m * N;
                 sh.buf[m * T + n] = make_double2(p.wtab[i], p.dwtab[i]);
             }
@@ -425,18 +443,35 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
             fft_stage_b<T, NT>(sh.buf + 2048, 32, 1, 32, tidv);
             __syncthreads();
             if (mine && present) {
-                // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f)
+                // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f); kBatch
+                // samples per lane in flight
                 const double2* zg = sh.buf + grid * 2048;
-                for (int i = lane; i < MN; i += 64) {
-                    float gv = 0.0f;
-                    if (live && known_at(p.known, p.target, ab, i)) {
-                        const int m = i / N, n = i - m * N;
-                        const double2 v = zg[FftPlan<T>::perm(m) * 32 + FftPlan<32>::perm(n >> 1)];
-                        const double wfb = (n & 1) ? v.y : v.x;
-                        gv = (float)(p.wtab[i] * wfb);
-                        racc += p.dwtab[i] * (double)p.areas[ab + i] * wfb;
+                for (int i0 = lane; i0 < MN; i0 += 64 * kBatch) {
+                    double w[kBatch], dw[kBatch];
+                    float x[kBatch];
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u) {
+                        const int i = i0 + 64 * u;
+                        const bool in = live && i < MN;
+                        w[u] = in ? p.wtab[i] : 0.0;
+                        dw[u] = in ? p.dwtab[i] : 0.0;
+                        x[u] = in ? p.areas[ab + i] : 0.0f;
                     }
-                    if (p.grad_areas) p.grad_areas[ab + i] = gv;
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u) {
+                        const int i = i0 + 64 * u;
+                        if (i < MN) {
+                            float gv = 0.0f;
+                            if (live && sh.mask[i]) {
+                                const int m = i / N, n = i - m * N;
+                                const double2 v = zg[FftPlan<T>::perm(m) * 32 + FftPlan<32>::perm(n >> 1)];
+                                const double wfb = (n & 1) ? v.y : v.x;
+                                gv = (float)(w[u] * wfb);
+                                racc += dw[u] * (double)x[u] * wfb;
+                            }
+                            if (p.grad_areas) p.grad_areas[ab + i] = gv;
+                        }
+                    }
                 }
             }
         }

@@ -111,14 +111,12 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
         if (p.known) a = a && (p.known[area_base + i] != 0);
         double w = 0.0, wf = 0.0;
         if (a) {
-            const float fv = p.areas[area_base + i];
-            // exponent all ones = Inf or NaN (tested on the bits: the library is
-            // compiled without NaN semantics for its min/max)
-            if ((__float_as_uint(fv) & 0x7f800000u) == 0x7f800000u) {
+            const uint32_t fb = sample_bits(p.areas, area_base + i);
+            if (nonfinite_bits(fb)) {
                 atomicOr(&s_flags, FOFSE_BLOCK_NONFINITE);
             } else {
                 w = p.wtab[i];
-                wf = w * (double)fv;
+                wf = w * (double)__uint_as_float(fb);
             }
         }
         win[n * T + m] = make_double2(w, wf);

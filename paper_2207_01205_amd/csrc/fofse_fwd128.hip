@@ -309,12 +309,12 @@ __global__ __launch_bounds__(NW * 64, 1) void fofse_fwd128_kernel(KParams p) {
     // eqs. 4, 7, 8: R from w f (a non-finite known sample flags the block)
     row_half_spectrum(sh, M, N, tid, [&](int i) -> double {
         if (!support(i)) return 0.0;
-        const float fv = p.areas[ab + i];
-        if ((__float_as_uint(fv) & 0x7f800000u) == 0x7f800000u) {
+        const uint32_t fb = sample_bits(p.areas, ab + i);
+        if (nonfinite_bits(fb)) {
             atomicOr(&sh.flags, FOFSE_BLOCK_NONFINITE);
             return 0.0;
         }
-        return p.wtab[i] * (double)fv;
+        return p.wtab[i] * (double)__uint_as_float(fb);
     });
     const int flags_pre = sh.flags;
     auto wval = [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; };

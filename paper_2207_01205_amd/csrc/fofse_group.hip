@@ -268,9 +268,9 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
                 const int m = i / N, n = i - m * N;
                 double fw = 0.0;
                 if (wreg[q] != 0.0) {
-                    const float x = p.areas[(size_t)blk[j] * MN + i];
-                    if ((__float_as_uint(x) & 0x7f800000u) == 0x7f800000u) atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
-                    else fw = wreg[q] * (double)x;
+                    const uint32_t xb = sample_bits(p.areas, (size_t)blk[j] * MN + i);
+                    if (nonfinite_bits(xb)) atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
+                    else fw = wreg[q] * (double)__uint_as_float(xb);
                 }
                 win[n * T + m] = make_double2(fw, 0.0);        // transposed placement
             }
