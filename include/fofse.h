@@ -191,7 +191,9 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  *   d_sel, d_coef  : device int32 [n_blocks][K] and double [n_blocks][K][2], the
  *                    record written by the forward call on these inputs (class
  *                    keys u*T+v and coefficients c).  Keys are read modulo the
- *                    grid, so any key yields a defined result.
+ *                    grid, so any key yields a defined result; the imaginary
+ *                    part of a self-conjugate class's coefficient is taken as
+ *                    0, as the forward writes it.
  *   d_grad_out     : device float [n_blocks][nB], dL/dg on the samples of B
  *                    (layout of the forward's d_out).
  *   d_grad_areas   : device float [n_blocks][M*N] or NULL: dL/df, 0 off the

@@ -70,8 +70,11 @@ __global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BPa
     for (int i = tid; i < T * T; i += NT) buf[i] = make_double2(0.0, 0.0);
     const size_t rb = (size_t)b * K;
     for (int i = tid; i < K; i += NT) {
-        keyL[i] = p.sel[rb + i] & (T * T - 1);     // k * T + l, read modulo the grid
-        cL[i] = make_double2(p.coef[2 * (rb + i)], p.coef[2 * (rb + i) + 1]);
+        const int key = p.sel[rb + i] & (T * T - 1);   // k * T + l, read modulo the grid
+        keyL[i] = key;
+        // a self-conjugate class has a real coefficient (the forward writes 0)
+        const bool pr = KY::pair(KY::k(key), KY::l(key));
+        cL[i] = make_double2(p.coef[2 * (rb + i)], pr ? p.coef[2 * (rb + i) + 1] : 0.0);
     }
     if (tid == 0) s_flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();

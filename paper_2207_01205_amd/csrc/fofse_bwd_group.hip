@@ -38,33 +38,47 @@ namespace fofse {
 namespace {
 
 constexpr int kRC = kGroupBackwardMaxK / 64;   // row chunks per lane
-constexpr int kZeroOff = 64 * 64 * 16;         // byte offset of the zero entry after Z
 constexpr int kBatch = 6;                      // samples per lane with loads in flight
 
 __device__ __forceinline__ bool known_at(const uint8_t* known, const uint8_t* target, size_t base, int i) {
     return target[i] == 0 && (known == nullptr || known[base + i] != 0);
 }
 
-// class packed as k << 8 | l: self-conjugate when k and l are 0 or 32
-__device__ __forceinline__ bool packed_pair(int x) { return (x & 0x1F1F) != 0; }
+// A class (k, l) travels packed as k << 26 | l << 4: k << 10 in the high and
+// l << 4 in the low 16-bit half.  One packed 16-bit add or subtract then forms
+// both coordinates of u_nu +- u_mu with no borrow between them; the high half
+// wraps k modulo 64 by itself, the low half is masked, and (r >> 16) | (r & 0x3F0)
+// is the byte offset of Z[k][l] in the natural-order 64 x 64 table.
+__device__ __forceinline__ uint32_t pack_class(int k, int l) { return ((uint32_t)k << 26) | ((uint32_t)l << 4); }
+__device__ __forceinline__ int class_k(uint32_t x) { return (int)(x >> 26); }
+__device__ __forceinline__ int class_l(uint32_t x) { return (int)(x >> 4) & 63; }
+// self-conjugate when k and l are 0 or 32
+__device__ __forceinline__ bool packed_pair(uint32_t x) { return (x & ((31u << 26) | (31u << 4))) != 0; }
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ int zoff(uint32_t r) { return (int)((r >> 16) | (r & 0x3F0u)); }
 
 // exact power of two, -1022 <= n <= 1023
 __device__ __forceinline__ double pow2(int n) { return __hiloint2double((n + 1023) << 20, 0); }
 
 // The four samples of Z' a pair of classes needs: Z'[u_nu - u_mu],
-// Z'[u_mu - u_nu], Z'[u_nu + u_mu], Z'[-u_nu - u_mu] for the packed classes xs
-// (uniform, nu) and yd (per lane, mu); the last two read the zero entry when mu
-// is self-conjugate (it takes one term only).
+// Z'[u_mu - u_nu], Z'[u_nu + u_mu], Z'[-u_nu - u_mu] for the packed classes x
+// (uniform, nu; nx = -x) and y (per lane, mu).
 struct ZQ {
     double2 a, b, c, d;
 };
 
-__device__ __forceinline__ ZQ zgather(const double2* Z, int xs, int yd, bool pr) {
-    using ZO = ZOff<64>;
-    const int oa = ZO::off((xs | 128) - yd);
-    const int ob = ZO::off((yd | 128) - xs);
-    const int oc = pr ? ZO::off(xs + yd) : kZeroOff;
-    const int od = pr ? ZO::off(((64 << 8) | 128) - xs - yd) : kZeroOff;
+__device__ __forceinline__ ZQ zgather(const double2* Z, uint32_t x, uint32_t nx, uint32_t y) {
+    const int oa = zoff(pk_sub(x, y));
+    const int ob = zoff(pk_sub(y, x));
+    const int oc = zoff(pk_add(x, y));
+    const int od = zoff(pk_sub(nx, y));
     ZQ q;
     q.a = lds_at(Z, oa);
     q.b = lds_at(Z, ob);
@@ -77,6 +91,9 @@ __device__ __forceinline__ ZQ zgather(const double2* Z, int xs, int yd, bool pr)
 // (sr, si) = cbar_nu and 2 W[d] = Z[d] + conj Z[-d], 2 j D[d] = Z[d] - conj Z[-d]:
 //   cbar_mu -= sbar conj(W[u_nu - u_mu]) + conj(sbar) W[u_nu + u_mu]
 //   racc    -= Re(sbar conj(c_mu D[u_nu - u_mu])) + Re(sbar conj(conj(c_mu) D[u_nu + u_mu]))
+// A self-conjugate mu takes the first term of each line only; as u_mu = -u_mu
+// there, the second term equals the first (c_mu is real), so such a row runs
+// the same formula on a doubled cbar_mu and a halved c_mu.
 __device__ __forceinline__ void zapply(const ZQ& q, double sr, double si, double2 c, double2& cb,
                                        double& rr) {
     const double s1 = q.a.x + q.b.x, s2 = q.c.x + q.d.x;   // Re W[d], Re W[s] (scaled)
@@ -92,14 +109,14 @@ __device__ __forceinline__ void zapply(const ZQ& q, double sr, double si, double
 
 // The iterations of one block, row mu = lane + 64 r.
 struct Rows {
-    int yd[kRC];       // class, packed k << 8 | l
+    uint32_t x[kRC];   // class, packed
     bool pr[kRC];      // not self-conjugate (and a valid row)
-    double2 c[kRC];    // forward coefficient c_mu
-    double2 cb[kRC];   // cbar_mu: running, then final
+    double2 c[kRC];    // forward coefficient c_mu (halved for a self-conjugate class)
+    double2 cb[kRC];   // cbar_mu: running (doubled for a self-conjugate class), then final
 };
 
 struct BwdGroupShared {
-    double2 buf[64 * 64 + 1];   // H tables, then Z', then the output grids; + zero entry
+    double2 buf[64 * 64];       // H tables, then Z', then the output grids
     double2 tw[64];             // exp(-j 2 pi q / 64)
     double2 tw32[32];           // exp(-j 2 pi q / 32)
     int expo[kGroup];
@@ -111,36 +128,40 @@ struct BwdGroupShared {
 // gathered before the current step is computed.
 template <int r>
 __device__ __forceinline__ void sweep_chunk(Rows& R, const double2* Z, int lane, int nv, double& rr) {
-    auto step = [&](int j, int x, const ZQ& q) {
-        const double cr = readlane_f64(R.cb[r].x, j);
-        const double ci = packed_pair(x) ? readlane_f64(R.cb[r].y, j) : 0.0;
+    auto step = [&](int j, uint32_t x, const ZQ& q) {
+        double cr = readlane_f64(R.cb[r].x, j), ci = 0.0;
+        if (packed_pair(x)) ci = readlane_f64(R.cb[r].y, j);
+        else cr *= 0.5;                   // a self-conjugate row runs doubled
         if (lane < j) zapply(q, cr, ci, R.c[r], R.cb[r], rr);
     };
+    auto cls = [&](int j) { return (uint32_t)__builtin_amdgcn_readlane((int)R.x[r], j); };
     int j = nv - 1;
-    int xa = __builtin_amdgcn_readlane(R.yd[r], j);
-    ZQ qa = zgather(Z, xa, R.yd[r], R.pr[r]);
+    uint32_t xa = cls(j);
+    ZQ qa = zgather(Z, xa, pk_sub(0u, xa), R.x[r]);
     for (; j >= 1; j -= 2) {
-        const int xb = __builtin_amdgcn_readlane(R.yd[r], j - 1);
-        const ZQ qb = zgather(Z, xb, R.yd[r], R.pr[r]);
+        const uint32_t xb = cls(j - 1);
+        const ZQ qb = zgather(Z, xb, pk_sub(0u, xb), R.x[r]);
         step(j, xa, qa);
-        xa = __builtin_amdgcn_readlane(R.yd[r], max(j - 2, 0));
-        qa = zgather(Z, xa, R.yd[r], R.pr[r]);
+        xa = cls(max(j - 2, 0));
+        qa = zgather(Z, xa, pk_sub(0u, xa), R.x[r]);
         step(j - 1, xb, qb);
     }
     if (j == 0) step(0, xa, qa);
-    if (!R.pr[r]) R.cb[r].y = 0.0;        // final adjoint of a self-conjugate class is real
+    // final adjoint of a self-conjugate class: real, back to scale
+    if (!R.pr[r]) R.cb[r] = make_double2(0.5 * R.cb[r].x, 0.0);
 }
 
 // The finished chunk r applied to every lower chunk (all lanes, all rows valid).
 template <int r>
 __device__ __forceinline__ void cross_chunk(Rows& R, const double2* Z, int nv, double& rr) {
     for (int j = 0; j < nv; ++j) {
-        const int x = __builtin_amdgcn_readlane(R.yd[r], j);
+        const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)R.x[r], j);
+        const uint32_t nx = pk_sub(0u, x);
         const double cr = readlane_f64(R.cb[r].x, j);
         const double ci = readlane_f64(R.cb[r].y, j);
 #pragma unroll
         for (int r2 = 0; r2 < r; ++r2) {
-            const ZQ q = zgather(Z, x, R.yd[r2], R.pr[r2]);
+            const ZQ q = zgather(Z, x, nx, R.x[r2]);
             zapply(q, cr, ci, R.c[r2], R.cb[r2], rr);
         }
     }
@@ -197,7 +218,7 @@ __device__ __forceinline__ void cbar0_rows(const BParams& p, int bj, int lane, d
         const int rows = min(16, p.b_h - m0);
 #pragma unroll
         for (int r = 0; r < kRC; ++r) {
-            const int k = R.yd[r] >> 8, l = R.yd[r] & 63;
+            const int k = class_k(R.x[r]), l = class_l(R.x[r]);
             for (int i = 0; i < rows; ++i) {
                 const double2 hv = H[i * 64 + l];
                 const double2 t = tw[(k * (p.b_m0 + m0 + i)) & 63];
@@ -209,10 +230,9 @@ __device__ __forceinline__ void cbar0_rows(const BParams& p, int bj, int lane, d
     }
 #pragma unroll
     for (int r = 0; r < kRC; ++r) {
+        // mult Gbar (mult = 2 for a conjugate pair); a self-conjugate row runs doubled
         const bool valid = lane + 64 * r < K;
-        const bool sc = !packed_pair(R.yd[r]);
-        R.cb[r] = !valid ? make_double2(0.0, 0.0)
-                         : sc ? make_double2(acc[r].x, 0.0) : make_double2(2.0 * acc[r].x, 2.0 * acc[r].y);
+        R.cb[r] = valid ? make_double2(2.0 * acc[r].x, R.pr[r] ? 2.0 * acc[r].y : 0.0) : make_double2(0.0, 0.0);
     }
 }
 
@@ -229,7 +249,6 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
     const bool params_ok = param_ok(rho) && param_ok(gamma);
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
     for (int i = tid; i < 32; i += NT) sh.tw32[i] = p.twiddle[2 * i];
-    if (tid == 0) sh.buf[T * T] = make_double2(0.0, 0.0);
 
     const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
@@ -303,9 +322,11 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
                 key = p.sel[(size_t)bj * K + nu] & (T * T - 1);
                 c = make_double2(p.coef[2 * ((size_t)bj * K + nu)], p.coef[2 * ((size_t)bj * K + nu) + 1]);
             }
-            R.yd[r] = ((key >> 6) << 8) | (key & 63);
-            R.pr[r] = valid && packed_pair(R.yd[r]);
-            R.c[r] = c;
+            R.x[r] = pack_class(key >> 6, key & 63);
+            R.pr[r] = valid && packed_pair(R.x[r]);
+            // a self-conjugate class has a real coefficient (the forward writes 0
+            // for its imaginary part); halved, see zapply
+            R.c[r] = R.pr[r] ? c : make_double2(0.5 * c.x, 0.0);
             R.cb[r] = make_double2(0.0, 0.0);
         }
         if (present && flags == 0) cbar0_rows(p, bj, lane, sh.buf + wave * 1024, sh.tw, R, K);
@@ -362,7 +383,8 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
             chunk<0>(R, sh.buf, lane, K, racc);
 #pragma unroll
             for (int r = 0; r < kRC; ++r)
-                if (lane + 64 * r < K) tacc += R.cb[r].x * R.c[r].x + R.cb[r].y * R.c[r].y;
+                if (lane + 64 * r < K)
+                    tacc += (R.pr[r] ? 1.0 : 2.0) * (R.cb[r].x * R.c[r].x + R.cb[r].y * R.c[r].y);
         }
 
         // (w f)bar = Re FFT(Y), Y = conj(gamma / W0 cbar) summed per class.  Made
@@ -417,7 +439,7 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
                 for (int r = 0; r < kRC; ++r) {
                     if (lane + 64 * r < K) {
                         const double yr = 0.5 * gW * R.cb[r].x, yi = -0.5 * gW * R.cb[r].y;
-                        const int k = R.yd[r] >> 8, l = R.yd[r] & 63;
+                        const int k = class_k(R.x[r]), l = class_l(R.x[r]);
                         put(k, l, yr, yi);                       // Y / 2 at (k, l)
                         put((-k) & 63, (-l) & 63, yr, -yi);      // conj(Y) / 2 at (-k, -l)
                     }

@@ -166,3 +166,25 @@ def test_grouped_backward_edge_cases(frame_areas):
     ga4, grg4, gb4 = gpu_backward(plan, areas, known, 0.8, 0.5, keys, coef, gbar_b, "grouped repeat")
     assert np.array_equal(gb3, gb) and np.array_equal(grg3, grg)
     assert np.array_equal(ga4, ga) and np.array_equal(gb4, gb)
+
+
+@pytest.mark.parametrize("path", ["grouped", "split"])
+def test_backward_ignores_imaginary_part_of_self_conjugate_coefficients(frame_areas, path):
+    """The forward writes a real coefficient for a self-conjugate class; a record
+    with a non-zero imaginary part there gives the same gradients, bit for bit."""
+    A = frame_areas
+    sub = slice(40, 52)
+    f, kn = _support(A.areas[sub], A.known[sub], A.target)
+    ref = fofse(f, kn, 64, 0.8, 0.5, 120)
+    k, l = ref.keys // 64, ref.keys % 64
+    sc = ((k % 32) == 0) & ((l % 32) == 0)
+    assert sc.any()
+    coef2 = ref.coef.copy()
+    coef2[sc] += 7.0j
+    gbar_b = np.random.default_rng(5).normal(size=(12, int(A.target.sum()))).astype(np.float32)
+    plan = (_grouped if path == "grouped" else _split)(48, 48, 120, A.target)
+    ga, grg, gb = gpu_backward(plan, A.areas[sub], A.known[sub], 0.8, 0.5, ref.keys, ref.coef, gbar_b,
+                               f"{path} clean record")
+    ga2, grg2, gb2 = gpu_backward(plan, A.areas[sub], A.known[sub], 0.8, 0.5, ref.keys, coef2, gbar_b,
+                                  f"{path} imaginary parts on self-conjugate classes")
+    assert np.array_equal(ga, ga2) and np.array_equal(gb, gb2) and np.array_equal(grg, grg2)
