@@ -88,10 +88,11 @@ int32_t fofse_target_count(fofse_plan plan);
  *   FOFSE_PATH_SPLIT   one workgroup per block, the block's rows spread over
  *                      several wavefronts (lowest latency for few blocks);
  *   FOFSE_PATH_GROUPED blocks with identical support masks grouped on the device;
- *                      one wavefront per block, one shared W per workgroup
- *                      (highest throughput).  Needs fft_size 64; the
- *                      adjoint takes it for K <= 256 (one workgroup per block
- *                      above that).
+ *                      one shared W per workgroup (highest throughput).
+ *                      fft_size 64: four blocks per workgroup, one wavefront
+ *                      each; fft_size 128: two blocks per workgroup, four
+ *                      wavefronts each.  The adjoint takes it for fft_size 64
+ *                      and K <= 256 (one workgroup per block otherwise).
  * Returns FOFSE_ERR_ARG for a NULL plan or unknown path, FOFSE_ERR_UNSUPPORTED
  * if the grouped path cannot run this geometry.
  */

@@ -3,7 +3,7 @@
 For one plan and a sample batch, every organisation built for the plan's FFT
 size is timed on the device (HIP events on the caller's stream, after one
 warm-up call): the split path with each built number of wavefronts per block
-and, for T = 64, the grouped path.  The fastest is set on the plan.  The
+and, for T = 64 and 128, the grouped path.  The fastest is set on the plan.  The
 arithmetic is the same for every candidate (the selections and outputs agree
 up to the rounding of the initial transform), so the choice only affects time.
 """
@@ -19,7 +19,7 @@ SPLIT_WAVES = {16: (1, 2), 32: (1, 2, 4), 64: (2, 4, 8), 128: (8, 16)}
 def candidates(T: int):
     """(label, path, waves) of every organisation built for FFT size T."""
     out = [(f"split/{w}", F.FOFSE_PATH_SPLIT, w) for w in SPLIT_WAVES[T]]
-    if T == 64:
+    if T in (64, 128):
         out.append(("grouped", F.FOFSE_PATH_GROUPED, 0))
     return out
 

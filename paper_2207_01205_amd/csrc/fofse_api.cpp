@@ -93,8 +93,11 @@ void free_plan(fofse_plan p) {
     delete p;
 }
 
+// Grouped path: T = 64 (four blocks of one mask per workgroup) and T = 128
+// (two blocks of one mask per workgroup, areas up to 64 x 64).
 bool grouped_supported(const fofse_plan_s* p) {
-    return p->T == 64 && p->nB <= fofse::group_max_target_samples() && p->M * p->N <= 64 * 64;
+    return (p->T == 64 || p->T == 128) && p->nB <= fofse::group_max_target_samples() && p->M <= 64 &&
+           p->N <= 64;
 }
 
 // Workspace of the grouped path for n blocks: hash table of hsize slots
@@ -334,7 +337,8 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
             e = fofse::launch_clear(g, st);
             if (e != hipSuccess) return FOFSE_ERR_DEVICE;
         }
-        e = fofse::launch_grouped(k, g, p->n_cu, st, tm);
+        e = p->T == 128 ? fofse::launch_grouped128(k, g, p->n_cu, st, tm)
+                        : fofse::launch_grouped(k, g, p->n_cu, st, tm);
     } else {
         e = fofse::launch_forward(k, st, tm);
     }
@@ -396,7 +400,7 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     }
     hipStream_t st = (hipStream_t)stream;
     // grouped adjoint: same rule as the forward, for K up to its register capacity
-    const bool grouped_ok = grouped_supported(p) && p->K <= fofse::kGroupBackwardMaxK;
+    const bool grouped_ok = p->T == 64 && grouped_supported(p) && p->K <= fofse::kGroupBackwardMaxK;
     bool grouped = false;
     if (p->path == FOFSE_PATH_GROUPED) grouped = grouped_ok;
     else if (p->path == FOFSE_PATH_AUTO) grouped = grouped_ok && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu;

@@ -518,14 +518,15 @@ hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const Gr
     if (p.T != 64 || p.K > kGroupBackwardMaxK || p.M * p.N > 16 * 64 * kGroup) return hipErrorInvalidValue;
     hipError_t e = launch_weights(wp, stream);
     if (e != hipSuccess) return e;
+    GroupArgs ga = g;
+    ga.gsize = kGroup;
     if (!g.direct) {
-        e = launch_grouping(g, p.n_blocks, stream);
+        e = launch_grouping(ga, p.n_blocks, stream);
         if (e != hipSuccess) return e;
     }
     const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
     int grid = 2 * n_cu;
     if (grid > max_items) grid = max_items;
-    GroupArgs ga = g;
     ga.n_wg = grid;
     constexpr int NT = 64 * kGroup;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;

@@ -54,11 +54,12 @@ struct Shared128 {
 // Spectrum rows l = 0..64 of x (area values from ``val``, transposed placement)
 // into sh.spec: direct DFT over n for l <= 64, then 128-point FFTs over m.
 // ``val(i)`` gives the value of area sample i = m * N + n (0 outside A).
-template <int NW, class F>
-__device__ __forceinline__ void row_half_spectrum(Shared128<NW>& sh, int M, int N, int tid, F val) {
-    constexpr int NT = NW * 64;
+template <int NT, class F>
+__device__ __forceinline__ void row_half_spectrum(double2* spec, const double2* tw, int M, int N, int tid,
+                                                  F val) {
+    constexpr int NW = NT / 64;
     constexpr int NJ = (ROWS128 + NW - 1) / NW;             // output rows per thread
-    double* xs = reinterpret_cast<double*>(sh.spec);      // staging xs[n * 64 + m]
+    double* xs = reinterpret_cast<double*>(spec);         // staging xs[n * 64 + m]
     for (int i = tid; i < 64 * 64; i += NT) xs[i] = 0.0;
     __syncthreads();
     for (int i = tid; i < M * N; i += NT) {
@@ -76,7 +77,7 @@ __device__ __forceinline__ void row_half_spectrum(Shared128<NW>& sh, int M, int 
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const int l = lg + NW * j;
-            const double2 t = sh.tw[(l * n) & (T128 - 1)];
+            const double2 t = tw[(l * n) & (T128 - 1)];
             acc[j].x = fma(x, t.x, acc[j].x);
             acc[j].y = fma(x, t.y, acc[j].y);
         }
@@ -86,21 +87,21 @@ __device__ __forceinline__ void row_half_spectrum(Shared128<NW>& sh, int M, int 
     for (int j = 0; j < NJ; ++j) {
         const int l = lg + NW * j;
         if (l <= H128) {
-            sh.spec[l * T128 + m] = acc[j];
-            sh.spec[l * T128 + 64 + m] = make_double2(0.0, 0.0);
+            spec[l * T128 + m] = acc[j];
+            spec[l * T128 + 64 + m] = make_double2(0.0, 0.0);
         }
     }
     __syncthreads();
-    fft_stage_a<T128, NT>(sh.spec, sh.tw, ROWS128, T128, 1, tid);
+    fft_stage_a<T128, NT>(spec, tw, ROWS128, T128, 1, tid);
     __syncthreads();
-    fft_stage_b<T128, NT>(sh.spec, ROWS128, T128, 1, tid);
+    fft_stage_b<T128, NT>(spec, ROWS128, T128, 1, tid);
     __syncthreads();
     // FFT output order -> natural column order, one row per wavefront: all lanes
     // read the row before any lane writes it (a wavefront's LDS operations run
     // in program order), so no barrier is needed inside a row
     const int lane = tid & 63;
     for (int r = tid >> 6; r < ROWS128; r += NW) {
-        double2* row = sh.spec + r * T128;
+        double2* row = spec + r * T128;
         const double2 a = row[perm128(lane)], c = row[perm128(lane + 64)];
         row[lane] = a;
         row[lane + 64] = c;
@@ -108,16 +109,19 @@ __device__ __forceinline__ void row_half_spectrum(Shared128<NW>& sh, int M, int 
     __syncthreads();
 }
 
-// One wavefront's rows [k0, k0 + S) of the K iterations.
+// One wavefront's rows [k0, k0 + S) of the K iterations of one block; the NW
+// wavefronts of the block exchange their candidates through ``xchg`` (two
+// buffers) and meet at a workgroup barrier every iteration.  ``live`` = false
+// runs the same barriers and writes nothing (a missing or flagged block that
+// shares the workgroup with a live one).
 template <int NW, int WI>
 __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
                                             RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
-                                            Shared128<NW>& sh, const KParams& p, int b, int lane,
-                                            double gW0) {
+                                            const double2* Wb, Xchg<NW>* xchg, const KParams& p, int b,
+                                            int lane, double gW0, bool live = true) {
     constexpr int k0 = row_begin128<NW>(WI);
     constexpr int S = row_begin128<NW>(WI + 1) - k0;
     const int K = p.K;
-    const double2* Wb = sh.spec;
     int u = 0, v = 0;
     double cr = 0.0, ci = 0.0;
     const int c0 = lane, c1 = lane + 64;
@@ -210,7 +214,7 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - r
         wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
         const bool whalf = ((mlo >> 7) & 1u) == 0u;
         const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
-        Xchg<NW>& x = sh.xchg[it & 1];
+        Xchg<NW>& x = xchg[it & 1];
         if (lane == 0) {
             x.hi[WI] = mhi;
             x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
@@ -240,7 +244,7 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - r
         const bool selfc = (u == 0 || u == H128) && (v == 0 || v == H128);
         const double cre = wv.x * gW0;
         const double cim = selfc ? 0.0 : wv.y * gW0;
-        if (WI == 0 && lane == 0) {
+        if (live && WI == 0 && lane == 0) {
             const size_t r = (size_t)b * K + it;
             p.sel[r] = v * T128 + u;
             p.coef[2 * r] = cre;
@@ -268,11 +272,11 @@ __device__ __forceinline__ void wave128(Shared128<NW>& sh, const KParams& p, int
         R1.set(s, c.x, c.y);
     }
     __syncthreads();                                        // every wave has its rows
-    row_half_spectrum(sh, p.M, p.N, tid, wval);             // W, row half, in LDS
+    row_half_spectrum<NW * 64>(sh.spec, sh.tw, p.M, p.N, tid, wval);   // W, row half, in LDS
     const double W0 = sh.spec[0].x;
     int flags = sh.flags | flags_pre;
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
-    if (flags == 0) run_wave128<NW, WI>(R0, R1, sh, p, b, lane, gamma / W0);
+    if (flags == 0) run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg, p, b, lane, gamma / W0);
 }
 
 // dispatch wave w to its specialised instance
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(NW * 64, 1) void fofse_fwd128_kernel(KParams p) {
         return a;
     };
     // eqs. 4, 7, 8: R from w f (a non-finite known sample flags the block)
-    row_half_spectrum(sh, M, N, tid, [&](int i) -> double {
+    row_half_spectrum<NT>(sh.spec, sh.tw, M, N, tid, [&](int i) -> double {
         if (!support(i)) return 0.0;
         const uint32_t fb = sample_bits(p.areas, ab + i);
         if (nonfinite_bits(fb)) {
@@ -331,6 +335,151 @@ __global__ __launch_bounds__(NW * 64, 1) void fofse_fwd128_kernel(KParams p) {
         }
     }
     if (p.status && tid == 0) p.status[b] = flags;
+}
+
+// ---------------------------------------------------------------------------
+// grouped T = 128: two blocks of one support mask per workgroup share the row
+// half of W in LDS (eqs. 4 and 15 depend on the mask only); each block has
+// kWaves128G wavefronts, so a compute unit iterates two blocks at once
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kBlocks128G = 2;
+constexpr int kWaves128G = 4;
+
+struct Shared128G {
+    double2 spec[ROWS128 * T128];
+    double2 tw[T128];
+    Xchg<kWaves128G> xchg[kBlocks128G][2];
+    int flags[kBlocks128G];
+};
+
+// One work item as seen by wave WI of block slot jb.  Every wave of the
+// workgroup runs the same sequence of barriers.
+template <int WI>
+__device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const GroupArgs& g, int item, int tid,
+                                        int lane, int jb, bool params_ok, double gamma) {
+    constexpr int NW = kWaves128G, NT = kBlocks128G * NW * 64;
+    constexpr int k0 = row_begin128<NW>(WI);
+    constexpr int S = row_begin128<NW>(WI + 1) - k0;
+    const int M = p.M, N = p.N, MN = M * N, K = p.K;
+    int nblk, b0, b1;
+    if (g.direct) {
+        nblk = min(kBlocks128G, p.n_blocks - item * kBlocks128G);
+        b0 = item * kBlocks128G;
+        b1 = b0 + 1;
+    } else {
+        nblk = g.item_n[item];
+        b0 = g.item_blk[(size_t)item * kGroup];
+        b1 = g.item_blk[(size_t)item * kGroup + 1];
+    }
+    const size_t rep = (size_t)b0 * MN;          // every block of the item has this mask
+    const bool present = jb < nblk;
+    const int bj = present ? (jb == 0 ? b0 : b1) : 0;
+    auto support = [&](int i) -> bool {
+        bool a = p.target[i] == 0;
+        if (p.known) a = a && p.known[rep + i] != 0;
+        return a;
+    };
+    __syncthreads();                              // previous item done with LDS
+    if (tid < kBlocks128G) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+
+    // eqs. 4, 7, 8: R of each block by its own transform; its waves take their rows
+    RegSpec<S> R0, R1;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        R0.set(s, 0.0, 0.0);
+        R1.set(s, 0.0, 0.0);
+    }
+    for (int j = 0; j < kBlocks128G; ++j) {
+        if (j >= nblk) break;                     // uniform over the workgroup
+        const size_t ab = (size_t)(j == 0 ? b0 : b1) * MN;
+        row_half_spectrum<NT>(sh.spec, sh.tw, M, N, tid, [&](int i) -> double {
+            if (!support(i)) return 0.0;
+            const uint32_t fb = sample_bits(p.areas, ab + i);
+            if (nonfinite_bits(fb)) {
+                atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
+                return 0.0;
+            }
+            return p.wtab[i] * (double)__uint_as_float(fb);
+        });
+        if (jb == j) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double2* row = sh.spec + (k0 + s) * T128;
+                const double2 a = row[lane], c = row[lane + 64];
+                R0.set(s, a.x, a.y);
+                R1.set(s, c.x, c.y);
+            }
+        }
+        __syncthreads();                          // rows taken before the next transform
+    }
+    row_half_spectrum<NT>(sh.spec, sh.tw, M, N, tid,
+                          [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; });
+    const double W0 = sh.spec[0].x;
+    int flags = sh.flags[jb];
+    if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
+    const bool live = present && flags == 0;
+    run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg[jb], p, bj, lane, live ? gamma / W0 : 0.0, live);
+    if (present && !live) {                       // empty record: the synthesised model is 0
+        for (int it = WI * 64 + lane; it < K; it += NW * 64) {
+            p.sel[(size_t)bj * K + it] = 0;
+            p.coef[2 * ((size_t)bj * K + it)] = 0.0;
+            p.coef[2 * ((size_t)bj * K + it) + 1] = 0.0;
+        }
+    }
+    if (present && p.status && WI == 0 && lane == 0) p.status[bj] = flags;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128_group_kernel(KParams p,
+                                                                                               GroupArgs g) {
+    constexpr int NT = kBlocks128G * kWaves128G * 64;
+    __shared__ Shared128G sh;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int jb = wave / kWaves128G, wi = wave % kWaves128G;
+    const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
+    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    for (int i = tid; i < T128; i += NT) sh.tw[i] = p.twiddle[i];
+    // items of this workgroup: a contiguous range
+    const int n_items = g.direct ? (p.n_blocks + kBlocks128G - 1) / kBlocks128G : g.counts[1];
+    const int per = (n_items + g.n_wg - 1) / g.n_wg;
+    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+    const int i1 = min(n_items, i0 + per);
+    static_assert(kWaves128G == 4, "one instance per wave of a block");
+    for (int item = i0; item < i1; ++item) {
+        if (wi == 0) item128<0>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        else if (wi == 1) item128<1>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        else if (wi == 2) item128<2>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        else item128<3>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+    }
+}
+
+hipError_t launch_grouped128(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
+                             const Timing& tm) {
+    if (p.T != 128 || p.M > 64 || p.N > 64) return hipErrorInvalidValue;
+    hipError_t e = launch_weights(p, stream);
+    if (e != hipSuccess) return e;
+    GroupArgs ga = g;
+    ga.gsize = kBlocks128G;
+    if (!g.direct) {
+        e = launch_grouping(ga, p.n_blocks, stream);
+        if (e != hipSuccess) return e;
+    }
+    const int max_items = g.direct ? (p.n_blocks + kBlocks128G - 1) / kBlocks128G : p.n_blocks;
+    int grid = n_cu;
+    if (grid > max_items) grid = max_items;
+    ga.n_wg = grid;
+    if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
+    hipLaunchKernelGGL(fofse_fwd128_group_kernel, dim3(grid), dim3(kBlocks128G * kWaves128G * 64), 0, stream, p,
+                       ga);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
+    return launch_synthesis(p, stream);
 }
 
 hipError_t launch_fwd128(const KParams& p, hipStream_t stream) {

@@ -12,7 +12,7 @@
 //   k_group_count exact byte comparison with the representative; position of
 //                 the block inside its class (blocks that differ from their
 //                 representative on a hash collision become singletons)
-//   k_group_scan  work items per class (ceil(count / kGroup)) -> item offsets
+//   k_group_scan  work items per class (ceil(count / gsize)) -> item offsets
 //   k_group_fill  item -> list of its blocks
 // The main kernel is persistent: workgroup g processes a contiguous range of
 // items, so consecutive items of one class land on the same workgroup.
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
     const int per = (g.hsize + 1023) / 1024;
     const int s0 = tid * per;
     int sum = 0;
-    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + kGroup - 1) / kGroup;
+    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + g.gsize - 1) / g.gsize;
     part[tid] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {       // inclusive scan (Hillis-Steele)
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
     int run = part[tid] - sum;
     for (int s = s0; s < s0 + per && s < g.hsize; ++s) {
         g.item_start[s] = run;
-        run += (g.ht_cnt[s] + kGroup - 1) / kGroup;
+        run += (g.ht_cnt[s] + g.gsize - 1) / g.gsize;
     }
     if (tid == 1023) {
         g.counts[0] = part[1023];                    // grouped items
@@ -131,10 +131,10 @@ __global__ void k_group_fill(GroupArgs g, int n) {
     const int pos = g.pos[b];
     int item, j, cnt;
     if (slot >= 0) {
-        item = g.item_start[slot] + pos / kGroup;
-        j = pos % kGroup;
-        const int c = g.ht_cnt[slot] - (pos / kGroup) * kGroup;
-        cnt = c < kGroup ? c : kGroup;
+        item = g.item_start[slot] + pos / g.gsize;
+        j = pos % g.gsize;
+        const int c = g.ht_cnt[slot] - (pos / g.gsize) * g.gsize;
+        cnt = c < g.gsize ? c : g.gsize;
     } else {
         item = g.counts[0] + pos;
         j = 0;
@@ -394,8 +394,10 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
     if (p.T != 64) return hipErrorInvalidValue;
     const hipError_t ew = launch_weights(p, stream);
     if (ew != hipSuccess) return ew;
+    GroupArgs ga = g;
+    ga.gsize = kGroup;
     if (!g.direct) {
-        const hipError_t eg = launch_grouping(g, p.n_blocks, stream);
+        const hipError_t eg = launch_grouping(ga, p.n_blocks, stream);
         if (eg != hipSuccess) return eg;
     }
     const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
@@ -403,7 +405,6 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
     if (grid > max_items) grid = max_items;
     constexpr int NT = kGroup * kWavesG * 64;
     const int mn = p.M * p.N;
-    GroupArgs ga = g;
     ga.n_wg = grid;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
     if (mn <= 9 * NT) hipLaunchKernelGGL((fofse_group_kernel<64, 9>), dim3(grid), dim3(NT), 0, stream, p, ga);

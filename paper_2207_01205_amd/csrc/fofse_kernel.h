@@ -72,6 +72,7 @@ constexpr int kGroupBackwardMaxK = 256;
 // Device workspace and arguments of the grouped path.
 struct GroupArgs {
     int direct;                       // 1: every block has the complement of B as support
+    int gsize;                        // blocks per work item (1..kGroup)
     int n_wg;                         // workgroups of the persistent main kernel
     int MN;                           // samples per area
     const uint8_t* known;             // [n][MN] or null
@@ -86,7 +87,7 @@ struct GroupArgs {
     int* pos;                         // [n] position inside the class / singleton index
     int* n_single;                    // [1]
     int* counts;                      // [2] grouped items, all items
-    int* item_blk;                    // [n][kGroup] blocks of a work item
+    int* item_blk;                    // [n][kGroup] blocks of a work item (first gsize used)
     int* item_n;                      // [n] blocks in the item
     int* item_cls;                    // [n] class of the item
 };
@@ -109,6 +110,8 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
                           const Timing& tm);
 hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
 hipError_t launch_fwd128(const KParams& p, hipStream_t stream);
+hipError_t launch_grouped128(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
+                             const Timing& tm);
 hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
                            const Timing& tm);
 // Mask classes and work items of n blocks (grouped forward and adjoint).

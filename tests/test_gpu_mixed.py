@@ -27,7 +27,11 @@ def _run(frame_img, cls_index, n, seed, waves=0):
     print(f"[gpu] mixed class {block}x{block}: n={n} area={A} T={T} K={K} waves={waves}", flush=True)
     dev = torch.device("cuda", 0)
     plan = Plan(A, A, T, K, target, device=0)
-    plan.set_waves(waves)
+    if waves == "grouped":
+        from paper_2207_01205_amd.fofse import FOFSE_PATH_GROUPED
+        plan.set_path(FOFSE_PATH_GROUPED)
+    else:
+        plan.set_waves(waves)
     a = torch.from_numpy(areas).to(dev)
     rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
     out, sel, coef, st = plan.extrapolate(a, rg, record=True)
@@ -72,10 +76,11 @@ def test_mixed_class_forward_and_adjoint(frame_img, cls_index):
         assert gb[i, 1] == pytest.approx(adj.gamma_bar, rel=1e-6, abs=1e-9 * scale)
 
 
-@pytest.mark.parametrize("waves", [8, 16])
+@pytest.mark.parametrize("waves", [8, 16, "grouped"])
 def test_mixed_class_128_forward(frame_img, waves):
     """32 x 32 losses in 64 x 64 areas, 128-point DFT, K = 300 (row-half
-    spectra, 8 or 16 wavefronts per block)."""
+    spectra; 8 or 16 wavefronts per block, or two blocks of four wavefronts
+    sharing W)."""
     plan, areas, target, truth, out, sel, coef, st, ref, f, kn = _run(frame_img, 3, 8, 103, waves)
     assert np.all(st == 0)
     ok, div = selection_parity(sel, ref.keys, ref.margin, 1e-6, top_ref=ref.top)
@@ -89,9 +94,12 @@ def test_mixed_class_128_forward(frame_img, waves):
           f"max|dc| {np.abs(coef - c_ref)[same].max():.2e}", flush=True)
 
 
-def test_128_irregular_masks_and_flags(frame_img):
+@pytest.mark.parametrize("path", ["split", "grouped"])
+def test_128_irregular_masks_and_flags(frame_img, path):
     """T = 128 with irregular support masks, a block without support, a NaN
-    known sample, and the adjoint reporting the size as unsupported."""
+    known sample, and the adjoint reporting the size as unsupported.  Blocks 0
+    and 2 share a mask (on the grouped path a live block next to a flagged
+    one), as do blocks 3 and 4; block 1 is alone."""
     from paper_2207_01205_amd import fofse as F
     block, support, T, K = synth.MIXED_CLASSES[3]
     areas, target, truth, _ = synth.mixed_blocks(frame_img, 77, block, support, 5)
@@ -100,9 +108,12 @@ def test_128_irregular_masks_and_flags(frame_img):
     known[1] = 0
     areas[2, 3, 3] = np.nan
     known[2, 3, 3] = 1
+    known[0] = known[2]
+    known[4] = known[3]
     dev = torch.device("cuda", 0)
     plan = F.Plan(64, 64, T, 60, target, device=0)
-    print("[gpu] T=128 irregular masks and flags", flush=True)
+    plan.set_path(F.FOFSE_PATH_GROUPED if path == "grouped" else F.FOFSE_PATH_SPLIT)
+    print(f"[gpu] T=128 irregular masks and flags, {path}", flush=True)
     out, sel, coef, st = plan.extrapolate(torch.from_numpy(areas).to(dev),
                                           torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev),
                                           known=torch.from_numpy(known).to(dev), record=True)
