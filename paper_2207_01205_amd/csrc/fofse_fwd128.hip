@@ -142,8 +142,10 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - r
                 const int s = q * CH + j;
                 if (s < S) {
                     const int k = k0 + s;
-                    const int rowA = k - u, rowB = k + u;
-                    const bool mirA = rowA < 0, mirB = rowB > H128;   // uniform
+                    // uniform rows, kept in scalar registers
+                    const int rowA = __builtin_amdgcn_readfirstlane(k - u);
+                    const int rowB = __builtin_amdgcn_readfirstlane(k + u);
+                    const bool mirA = rowA < 0, mirB = rowB > H128;
                     const double2* pA = Wb + (mirA ? -rowA : rowA) * T128;
                     const double2* pB = Wb + (mirB ? T128 - rowB : rowB) * T128;
                     xa[bf][j][0] = pA[mirA ? mA0 : dA0];
@@ -163,21 +165,24 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - r
                 const int s = q * CH + j;
                 if (s >= S) break;
                 const int k = k0 + s;
-                const bool mirA = k - u < 0, mirB = k + u > H128;
-                // R -= c W1 + conj(c) W2 with W1 = xa or conj(xa), W2 = xb or conj(xb)
-                const double ciA = neg_if(mirA, ci), crA = neg_if(mirA, cr);
-                const double ciB = neg_if(mirB, ci), crB = neg_if(mirB, cr);
+                // R -= c W1 + conj(c) W2 with W1 = xa or conj(xa), W2 = xb or conj(xb):
+                // a mirrored read is conjugated by flipping the sign bit of its
+                // imaginary part in place (uniform masks, one integer op per read)
+                const uint32_t sgA = __builtin_amdgcn_readfirstlane(k - u) < 0 ? 0x80000000u : 0u;
+                const uint32_t sgB = __builtin_amdgcn_readfirstlane(k + u) > H128 ? 0x80000000u : 0u;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const double2 x1 = xa[q & 1][j][h], x2 = xb[q & 1][j][h];
+                    const double y1 = __hiloint2double(__double2hiint(x1.y) ^ (int)sgA, __double2loint(x1.y));
+                    const double y2 = __hiloint2double(__double2hiint(x2.y) ^ (int)sgB, __double2loint(x2.y));
                     double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
                     const double sr = x1.x + x2.x, dr = x1.x - x2.x;
                     re = fma(-cr, sr, re);
-                    re = fma(ciA, x1.y, re);
-                    re = fma(-ciB, x2.y, re);
+                    re = fma(ci, y1, re);
+                    re = fma(-ci, y2, re);
                     im = fma(-ci, dr, im);
-                    im = fma(-crA, x1.y, im);
-                    im = fma(-crB, x2.y, im);
+                    im = fma(-cr, y1, im);
+                    im = fma(-cr, y2, im);
                     if (h) R1.set(s, re, im); else R0.set(s, re, im);
                     // eq. 9 key: |R|^2, then column half (0 first), then smaller row
                     const double m2 = sq_add(im, re * re);
