@@ -331,6 +331,7 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         g.known = d_known;
         g.target = p->d_target;
         g.direct = d_known == nullptr;
+        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
         if (!g.direct) {
             const fofse_status ws = ensure_workspace(p, n_blocks, g);
             if (ws != FOFSE_OK) return ws;
@@ -411,6 +412,7 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         g.known = d_known;
         g.target = p->d_target;
         g.direct = d_known == nullptr;
+        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
         if (!g.direct) {
             const fofse_status ws = ensure_workspace(p, n_blocks, g);
             if (ws != FOFSE_OK) return ws;

@@ -520,6 +520,7 @@ hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const Gr
     if (e != hipSuccess) return e;
     GroupArgs ga = g;
     ga.gsize = kGroup;
+    ga.gshift = kGroupShift;
     if (!g.direct) {
         e = launch_grouping(ga, p.n_blocks, stream);
         if (e != hipSuccess) return e;

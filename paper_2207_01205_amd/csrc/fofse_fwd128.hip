@@ -469,7 +469,9 @@ hipError_t launch_grouped128(const KParams& p, const GroupArgs& g, int n_cu, hip
     hipError_t e = launch_weights(p, stream);
     if (e != hipSuccess) return e;
     GroupArgs ga = g;
+    static_assert(kBlocks128G == 2, "item size 2 = 1 << 1");
     ga.gsize = kBlocks128G;
+    ga.gshift = 1;
     if (!g.direct) {
         e = launch_grouping(ga, p.n_blocks, stream);
         if (e != hipSuccess) return e;

@@ -42,6 +42,19 @@ __device__ __forceinline__ bool eff_known(const uint8_t* known, const uint8_t* t
     return target[i] == 0 && (known == nullptr || known[base + i] != 0);
 }
 
+// Support bits of 16 consecutive samples from 16 bytes of the known mask and 16
+// of the target mask: bit j set when sample 16 c + j is known and off B.
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t x) {      // high bit of each non-zero byte
+    return (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+}
+__device__ __forceinline__ uint32_t pack_hi_bits(uint32_t e) {  // bits 7, 15, 23, 31 -> 0..3
+    return ((e >> 7) & 1u) | ((e >> 14) & 2u) | ((e >> 21) & 4u) | ((e >> 28) & 8u);
+}
+__device__ __forceinline__ uint32_t support_bits16(uint4 kn, uint4 tg) {
+    return pack_hi_bits(nz_bytes(kn.x) & ~nz_bytes(tg.x)) | (pack_hi_bits(nz_bytes(kn.y) & ~nz_bytes(tg.y)) << 4) |
+           (pack_hi_bits(nz_bytes(kn.z) & ~nz_bytes(tg.z)) << 8) | (pack_hi_bits(nz_bytes(kn.w) & ~nz_bytes(tg.w)) << 12);
+}
+
 __device__ __forceinline__ uint64_t wave_xor_u64(uint64_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -61,8 +74,15 @@ __global__ __launch_bounds__(64 * kHashBlocks) void k_mask_hash(GroupArgs g, int
     if (b >= n) return;
     const size_t base = (size_t)b * g.MN;
     uint64_t h = 0;
-    for (int i = lane; i < g.MN; i += 64)
-        if (eff_known(g.known, g.target, base, i)) h ^= mix64((uint64_t)i);
+    if (g.vec16) {          // 16 samples per load: hash of (chunk index, support bits)
+        const uint4* kn = reinterpret_cast<const uint4*>(g.known + base);
+        const uint4* tg = reinterpret_cast<const uint4*>(g.target);
+        for (int c = lane; c < (g.MN >> 4); c += 64)
+            h ^= mix64(((uint64_t)c << 16) | support_bits16(kn[c], tg[c]));
+    } else {
+        for (int i = lane; i < g.MN; i += 64)
+            if (eff_known(g.known, g.target, base, i)) h ^= mix64((uint64_t)i);
+    }
     h = wave_xor_u64(h) | 1ull;          // 0 marks an empty table slot
     if (lane == 0) {
         uint32_t slot = (uint32_t)(h >> 17) & g.hmask;
@@ -84,8 +104,18 @@ __global__ __launch_bounds__(64 * kHashBlocks) void k_group_count(GroupArgs g, i
     const int rep = g.ht_rep[slot];
     const size_t base = (size_t)b * g.MN, rbase = (size_t)rep * g.MN;
     bool same = true;
-    for (int i = lane; i < g.MN; i += 64)
-        same = same && (eff_known(g.known, g.target, base, i) == eff_known(g.known, g.target, rbase, i));
+    if (g.vec16) {
+        const uint4* kb = reinterpret_cast<const uint4*>(g.known + base);
+        const uint4* kr = reinterpret_cast<const uint4*>(g.known + rbase);
+        const uint4* tg = reinterpret_cast<const uint4*>(g.target);
+        for (int c = lane; c < (g.MN >> 4); c += 64) {
+            const uint4 t = tg[c];
+            same = same && support_bits16(kb[c], t) == support_bits16(kr[c], t);
+        }
+    } else {
+        for (int i = lane; i < g.MN; i += 64)
+            same = same && (eff_known(g.known, g.target, base, i) == eff_known(g.known, g.target, rbase, i));
+    }
     same = __all(same);
     if (lane == 0) {
         if (same) {
@@ -104,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
     const int per = (g.hsize + 1023) / 1024;
     const int s0 = tid * per;
     int sum = 0;
-    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + g.gsize - 1) / g.gsize;
+    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + g.gsize - 1) >> g.gshift;
     part[tid] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {       // inclusive scan (Hillis-Steele)
@@ -116,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
     int run = part[tid] - sum;
     for (int s = s0; s < s0 + per && s < g.hsize; ++s) {
         g.item_start[s] = run;
-        run += (g.ht_cnt[s] + g.gsize - 1) / g.gsize;
+        run += (g.ht_cnt[s] + g.gsize - 1) >> g.gshift;
     }
     if (tid == 1023) {
         g.counts[0] = part[1023];                    // grouped items
@@ -131,9 +161,9 @@ __global__ void k_group_fill(GroupArgs g, int n) {
     const int pos = g.pos[b];
     int item, j, cnt;
     if (slot >= 0) {
-        item = g.item_start[slot] + pos / g.gsize;
-        j = pos % g.gsize;
-        const int c = g.ht_cnt[slot] - (pos / g.gsize) * g.gsize;
+        item = g.item_start[slot] + (pos >> g.gshift);
+        j = pos & (g.gsize - 1);
+        const int c = g.ht_cnt[slot] - ((pos >> g.gshift) << g.gshift);
         cnt = c < g.gsize ? c : g.gsize;
     } else {
         item = g.counts[0] + pos;
@@ -396,6 +426,7 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
     if (ew != hipSuccess) return ew;
     GroupArgs ga = g;
     ga.gsize = kGroup;
+    ga.gshift = kGroupShift;
     if (!g.direct) {
         const hipError_t eg = launch_grouping(ga, p.n_blocks, stream);
         if (eg != hipSuccess) return eg;

@@ -65,6 +65,7 @@ constexpr int kBackwardMaxK = 2048;
 
 // Blocks per workgroup in the grouped path (they share one W).
 constexpr int kGroup = 4;
+constexpr int kGroupShift = 2;
 
 // Largest K of the grouped adjoint (K / 64 rows per lane in registers).
 constexpr int kGroupBackwardMaxK = 256;
@@ -72,7 +73,9 @@ constexpr int kGroupBackwardMaxK = 256;
 // Device workspace and arguments of the grouped path.
 struct GroupArgs {
     int direct;                       // 1: every block has the complement of B as support
-    int gsize;                        // blocks per work item (1..kGroup)
+    int gsize;                        // blocks per work item (1, 2 or kGroup)
+    int gshift;                       // log2(gsize)
+    int vec16;                        // MN % 16 == 0 and known 16-byte aligned: masks read 16 bytes at a time
     int n_wg;                         // workgroups of the persistent main kernel
     int MN;                           // samples per area
     const uint8_t* known;             // [n][MN] or null
