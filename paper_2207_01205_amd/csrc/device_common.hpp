@@ -100,12 +100,20 @@ struct FftPlan {
     __host__ __device__ static constexpr int perm(int k) { return 8 * (k % R1) + k / R1; }
 };
 
+// Tasks go to threads so that the lanes of a wavefront touch different LDS banks:
+// along contiguous lines (elem_stride 1) neighbouring lanes take neighbouring
+// elements of one line; across lines (elem_stride > 1, nlines a power of two)
+// neighbouring lanes take neighbouring lines (a lane-per-element mapping there
+// would put the lanes of a line T entries apart, all in one bank).
 template <int T, int NT>
 __device__ __forceinline__ void fft_stage_a(double2* buf, const double2* tw, int nlines,
                                             int line_stride, int elem_stride, int tid) {
     constexpr int R1 = FftPlan<T>::R1;
+    const bool across = elem_stride != 1;
+    const int lsh = __builtin_ctz(nlines);          // across lines, nlines is a power of two
     for (int task = tid; task < nlines * 8; task += NT) {
-        const int line = task >> 3, n2 = task & 7;
+        const int line = across ? task & (nlines - 1) : task >> 3;
+        const int n2 = across ? task >> lsh : task & 7;
         double2* base = buf + line * line_stride;
         double2 x[R1];
 #pragma unroll
@@ -123,8 +131,11 @@ template <int T, int NT>
 __device__ __forceinline__ void fft_stage_b(double2* buf, int nlines, int line_stride,
                                             int elem_stride, int tid) {
     constexpr int R1 = FftPlan<T>::R1;
+    const bool across = elem_stride != 1;
+    const int lsh = __builtin_ctz(nlines);          // across lines, nlines is a power of two
     for (int task = tid; task < nlines * R1; task += NT) {
-        const int line = task / R1, k1 = task - line * R1;
+        const int line = across ? task & (nlines - 1) : task / R1;
+        const int k1 = across ? task >> lsh : task - line * R1;
         double2* base = buf + line * line_stride + 8 * k1 * elem_stride;
         double2 x[8];
 #pragma unroll

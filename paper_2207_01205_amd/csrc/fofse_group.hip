@@ -203,9 +203,9 @@ __device__ __forceinline__ void fft64_stage_b_to_window(double2* win, int tid) {
     for (int half = 0; half < 2; ++half) {
         // half A first, then half B: the writes of a half only touch columns of
         // that half, whose inputs have all been read before the barrier
-        const int t = half * NT + tid;
-        const int pc = kColHalves[t >> 3];
-        const int k1 = t & 7;
+        // neighbouring lanes take different columns (different LDS banks)
+        const int pc = kColHalves[(half << 5) | (tid & 31)];
+        const int k1 = tid >> 5;
         double2 x[8];
 #pragma unroll
         for (int n2 = 0; n2 < 8; ++n2) x[n2] = win[(8 * k1 + n2) * T + pc];
