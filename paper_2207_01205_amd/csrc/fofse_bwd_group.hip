@@ -44,20 +44,22 @@ __device__ __forceinline__ bool known_at(const uint8_t* known, const uint8_t* ta
     return target[i] == 0 && (known == nullptr || known[base + i] != 0);
 }
 
-// Z' is stored skewed: entry (k, l) at column (l + k) mod 64 of row k, so that
-// the LDS bank of an entry depends on k + l rather than on l alone (the classes
-// of a record cluster at low l; unskewed, the gathers of a wave would pile onto
-// few banks).  A class travels packed as k << 26 | s << 4 with s = (l + k) mod
-// 64: k << 10 in the high and s << 4 in the low 16-bit half.  The skew is
+// Z' is stored skewed: entry (k, l) at column (l + 13 k) mod 64 of row k, so
+// that the LDS bank of an entry depends on k as well as l (the classes of a
+// record cluster at low frequencies; unskewed, the gathers of a wave pile onto
+// few banks; on frame records the multiplier 13 leaves about as many conflicts
+// as random addresses would).  A class travels packed as k << 26 | s << 4 with
+// s = (l + 13 k) mod 64: k << 10 in the high and s << 4 in the low 16-bit half.  The skew is
 // additive, so one packed 16-bit add or subtract forms both coordinates of the
 // skewed address of u_nu +- u_mu with no borrow between them; the high half
 // wraps k modulo 64 by itself, the low half is masked, and (r >> 16) | (r & 0x3F0)
 // is the byte offset in the 64 x 64 table.
+constexpr int kSkew = 13;
 __device__ __forceinline__ uint32_t pack_class(int k, int l) {
-    return ((uint32_t)k << 26) | ((uint32_t)((l + k) & 63) << 4);
+    return ((uint32_t)k << 26) | ((uint32_t)((l + kSkew * k) & 63) << 4);
 }
 __device__ __forceinline__ int class_k(uint32_t x) { return (int)(x >> 26); }
-__device__ __forceinline__ int class_l(uint32_t x) { return (int)((x >> 4) - (x >> 26)) & 63; }
+__device__ __forceinline__ int class_l(uint32_t x) { return (int)((x >> 4) - kSkew * (x >> 26)) & 63; }
 // self-conjugate when k and l are 0 or 32 (with k a multiple of 32, s = l mod 32)
 __device__ __forceinline__ bool packed_pair(uint32_t x) { return (x & ((31u << 26) | (31u << 4))) != 0; }
 
@@ -374,11 +376,11 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
         const bool live = present && flags == 0;
         const double hW = (params_ok && W0 > 0.0) ? 0.5 * gamma / W0 : 0.0;
-        // Z' = hW Z, each row k rotated by k columns (the skewed layout above);
+        // Z' = hW Z, each row k rotated by 13 k columns (the skewed layout above);
         // one wavefront per row: its lanes read the row before any writes it
         for (int r = (tidv >> 6); r < T; r += NT / 64) {
             const double2 z = sh.buf[r * T + lane];
-            sh.buf[r * T + ((lane + r) & (T - 1))] = make_double2(hW * z.x, hW * z.y);
+            sh.buf[r * T + ((lane + kSkew * r) & (T - 1))] = make_double2(hW * z.x, hW * z.y);
         }
         __syncthreads();
 
