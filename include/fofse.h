@@ -9,8 +9,9 @@
  * (eqs. 2-9 with the constant compensation of eq. 14) is the estimate of f on
  * the missing area B.  Weighting w = rho on A, 0 elsewhere (eq. 4), with the
  * isotropic model rho = rho_hat ** dist(centre) (eq. 15).  Basis functions:
- * the T x T two-dimensional DFT (Results section), handled entirely in the
- * transform domain.
+ * the T x T two-dimensional DFT (Results section) or, by fofse_set_basis, the
+ * T x T two-dimensional DCT (Section 2), handled entirely in the transform
+ * domain.
  *
  * Conventions shared by every entry point:
  *   - "device" pointers are HIP device memory of the plan's device; "host"
@@ -100,6 +101,32 @@ int32_t fofse_target_count(fofse_plan plan);
 #define FOFSE_PATH_SPLIT   1
 #define FOFSE_PATH_GROUPED 2
 fofse_status fofse_set_path(fofse_plan plan, int32_t path);
+
+/*
+ * Set of basis functions (Section 2: the DFT and the DCT both let the whole
+ * iteration run in the transform domain, after eq. 9):
+ *   FOFSE_BASIS_DFT (default) the T x T two-dimensional DFT, conjugate pairs
+ *                   (everything below describes this basis unless stated);
+ *   FOFSE_BASIS_DCT the orthonormal T x T DCT-II, phi_{k,l}[m,n] = a_k a_l
+ *                   cos(pi k (2m+1)/(2T)) cos(pi l (2n+1)/(2T)), a_0 = sqrt(1/T),
+ *                   a_k = sqrt(2/T), the area at the grid's origin.  Every
+ *                   iteration picks the basis function with the largest |R_w|
+ *                   among all T*T (eq. 9; ties to the smallest k*T + l), sets
+ *                   c = gamma R_w[u] / sum_A w phi_u^2 (eqs. 5, 14; the
+ *                   denominator depends on u) and removes c <w phi_u, phi_k> from
+ *                   every R_w[k] (eq. 3).  fofse_extrapolate_batch then writes
+ *                   keys k*T + l in [0, T*T) to d_sel and (c, 0) to d_coef;
+ *                   blocks with identical support masks share a workgroup,
+ *                   whatever the path setting.  fft_size 64 only; no adjoint.
+ * Results of one basis never depend on the other's settings.  Selecting the
+ * DCT uploads a T x T cosine table on first use (synchronous).
+ * Returns FOFSE_ERR_ARG for a NULL plan or unknown basis,
+ * FOFSE_ERR_UNSUPPORTED for the DCT with fft_size other than 64,
+ * FOFSE_ERR_NOMEM / FOFSE_ERR_DEVICE if the table cannot be uploaded.
+ */
+#define FOFSE_BASIS_DFT 0
+#define FOFSE_BASIS_DCT 1
+fofse_status fofse_set_basis(fofse_plan plan, int32_t basis);
 
 /*
  * Extrapolate n_blocks areas of the plan's geometry (Sections 2 and 3).
@@ -217,7 +244,8 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  *
  * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
  * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
- * FOFSE_ERR_UNSUPPORTED when K exceeds 2048 or T exceeds 64, FOFSE_ERR_NOMEM if
+ * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, T exceeds 64 or the plan's basis is
+ * the DCT (FOFSE_BASIS_DCT has no adjoint), FOFSE_ERR_NOMEM if
  * the per-block workspace (16 B per block, used when d_grad_block is NULL) or
  * the grouped path's workspace cannot be allocated, FOFSE_ERR_DEVICE if a
  * launch fails, FOFSE_OK otherwise.

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/fofse.h"
+#include "dct_kernel.h"
 #include "fofse_kernel.h"
 
 struct fofse_plan_s {
@@ -17,6 +18,8 @@ struct fofse_plan_s {
     int n_cu = 0;
     int path = FOFSE_PATH_AUTO;
     int waves = 0;                  // split path: wavefronts per block (0 = default)
+    int basis = FOFSE_BASIS_DFT;
+    double* d_dct_cos = nullptr;    // DCT basis: cos(pi k (2m+1) / (2T)) at [m * T + k]
     int M = 0, N = 0, T = 0, K = 0, nB = 0;
     uint8_t* d_target = nullptr;
     int32_t* d_bpix = nullptr;
@@ -90,6 +93,7 @@ void free_plan(fofse_plan p) {
     if (p->d_wtab) (void)hipFree(p->d_wtab);
     if (p->d_dwtab) (void)hipFree(p->d_dwtab);
     if (p->d_gblk) (void)hipFree(p->d_gblk);
+    if (p->d_dct_cos) (void)hipFree(p->d_dct_cos);
     delete p;
 }
 
@@ -238,6 +242,31 @@ fofse_status fofse_set_path(fofse_plan p, int32_t path) {
     return FOFSE_OK;
 }
 
+fofse_status fofse_set_basis(fofse_plan p, int32_t basis) {
+    if (!p || (basis != FOFSE_BASIS_DFT && basis != FOFSE_BASIS_DCT)) return FOFSE_ERR_ARG;
+    if (basis == FOFSE_BASIS_DCT) {
+        if (p->T != fofse::kDctT) return FOFSE_ERR_UNSUPPORTED;
+        if (!p->d_dct_cos) {
+            const int T = p->T;
+            std::vector<double> c((size_t)T * T);
+            for (int m = 0; m < T; ++m)
+                for (int k = 0; k < T; ++k)
+                    c[(size_t)m * T + k] = std::cos(M_PI * (double)k * (2.0 * m + 1.0) / (2.0 * T));
+            DeviceGuard guard(p->device);
+            if (!guard.ok) return FOFSE_ERR_DEVICE;
+            double* d = nullptr;
+            if (hipMalloc(&d, c.size() * sizeof(double)) != hipSuccess) return FOFSE_ERR_NOMEM;
+            if (hipMemcpy(d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipFree(d);
+                return FOFSE_ERR_DEVICE;
+            }
+            p->d_dct_cos = d;
+        }
+    }
+    p->basis = basis;
+    return FOFSE_OK;
+}
+
 fofse_status fofse_set_waves(fofse_plan p, int32_t waves) {
     if (!p || waves < 0) return FOFSE_ERR_ARG;
     if (!fofse::split_waves_built(p->T, waves)) return FOFSE_ERR_UNSUPPORTED;
@@ -313,6 +342,28 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         if (!d_coef) k.coef = p->d_rec_coef;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (p->basis == FOFSE_BASIS_DCT) {
+        fofse::Timing tm{};
+        if (p->timing) {
+            const int i = (int)(p->n_timed % kRing);
+            tm.start = p->ev_start[i];
+            tm.stop = p->ev_stop[i];
+            ++p->n_timed;
+        }
+        fofse::GroupArgs g{};
+        g.MN = p->M * p->N;
+        g.known = d_known;
+        g.target = p->d_target;
+        g.direct = d_known == nullptr;
+        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        if (!g.direct) {
+            const fofse_status ws = ensure_workspace(p, n_blocks, g);
+            if (ws != FOFSE_OK) return ws;
+            if (fofse::launch_clear(g, st) != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        const hipError_t e = fofse::launch_dct(k, g, p->d_dct_cos, p->n_cu, st, tm);
+        return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
+    }
     bool grouped = false;
     if (p->path == FOFSE_PATH_GROUPED) grouped = true;
     else if (p->path == FOFSE_PATH_AUTO)
@@ -354,7 +405,7 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
     if (n_blocks == 0) return FOFSE_OK;
     if (!d_areas || !d_rho_gamma || !d_sel || !d_coef || !d_grad_out) return FOFSE_ERR_ARG;
-    if (p->K > fofse::kBackwardMaxK || p->T > 64) return FOFSE_ERR_UNSUPPORTED;
+    if (p->K > fofse::kBackwardMaxK || p->T > 64 || p->basis != FOFSE_BASIS_DFT) return FOFSE_ERR_UNSUPPORTED;
     DeviceGuard guard(p->device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;
     double* blk = d_grad_block;

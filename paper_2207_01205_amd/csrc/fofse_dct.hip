@@ -1,0 +1,374 @@
+// FOFSE with the two-dimensional DCT as its set of basis functions: the
+// variant that, like the DFT one, runs entirely in the transform domain
+// (Section 2, after eq. 9).
+//
+// Basis phi_{k,l}[m,n] = a_k a_l C(k, m) C(l, n), C(a, m) = cos(pi a (2m+1) /
+// (2T)), a_0 = sqrt(1/T), a_k = sqrt(2/T): the orthonormal DCT-II of the T x T
+// grid (T = 64), the area at its origin.  Per block:
+//   R = DCT(w f)                                          (eqs. 7, 8)
+//   K times: u = argmax |R|, ties to the smallest k*T + l  (eq. 9)
+//            c = gamma R[u] / <phi_u, phi_u>_w             (eqs. 5, 14)
+//            R[k] -= c <w phi_u, phi_k> for every k        (eq. 3)
+//   g on B = sum of c phi_u                                (eqs. 1, 2)
+//
+// Gram entries from one table.  cos x cos y = (cos(x - y) + cos(x + y)) / 2 in
+// each dimension gives
+//   <w phi_u, phi_k> = a_k1 a_k2 a_u1 a_u2 / 4 * sum_{s1,s2 = +-1} Wc[k1 + s1 u1][k2 + s2 u2]
+// with Wc[a][b] = sum_A w C(a, m) C(b, n).  As C(-a) = C(a), C(2T - a) = -C(a)
+// and C(T) = 0, every index in (-T, 2T) folds into [0, T] with a sign, so the
+// table holds Wc on [0, T] x [0, T] (row and column T are zero).
+//
+// Organisation.  One wavefront per block: lane = column index l, register slot
+// = row index k (64 doubles per lane).  Blocks with one support mask share w
+// and so the table; a workgroup takes up to four of them (the work items of
+// the device-side grouping) and builds the table once.  Per iteration a lane
+// reads four table entries per slot: two columns (|l - v| and the fold of
+// l + v, fixed for the lane) in two rows (|k - u| and the fold of k + u,
+// uniform for the slot).  The iteration loop has no barrier.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dct_kernel.h"
+#include "device_common.hpp"
+
+namespace fofse {
+
+namespace {
+
+constexpr int kT = kDctT;
+constexpr int kTP = kT + 1;                 // table row stride; index T holds 0
+constexpr int kNT = 64 * kGroup;            // one wavefront per block
+constexpr int kBufLen = kT * kTP;           // >= T * T
+constexpr double kA0 = 0.125;               // sqrt(1/64)
+constexpr double kA1 = 0.1767766952966369;  // sqrt(2/64)
+constexpr int kAhead = 3;                   // slots whose table reads are in flight
+
+typedef double d16 __attribute__((ext_vector_type(16)));
+
+struct DctShared {
+    double tab[kTP * kTP];   // Wc; while the blocks are transformed: one block's R at [k * T + l]
+    double buf[kBufLen];     // column pass at [n * kTP + k]; during the iterations C(u, m) at [m * T + u]
+    int flags[kGroup];
+};
+
+__device__ __forceinline__ bool known_sample(const uint8_t* known, const uint8_t* target, size_t base, int i) {
+    return target[i] == 0 && (known == nullptr || known[base + i] != 0);
+}
+
+// P[n][k] = sum_m C(k, m) X[m][n] for n < N and the 16 rows k of wave wv, with
+// X = w on the support of the item's mask, times f of block b when b >= 0.
+// Written to buf[n * kTP + k].  A non-finite known sample of block b sets
+// FOFSE_BLOCK_NONFINITE in *flag (its contribution is 0).
+__device__ __forceinline__ void column_pass(double* buf, const KParams& p, const GroupArgs& g, size_t rep_base,
+                                            int b, int* flag, const double* __restrict__ cosm, int wv, int lane) {
+    const int M = p.M, N = p.N, MN = M * N;
+    const bool col = lane < N;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int m = 0; m < M; ++m) {
+        double x = 0.0;
+        if (col) {
+            const int i = m * N + lane;
+            if (known_sample(g.known, p.target, rep_base, i)) {
+                const double w = p.wtab[i];
+                if (b < 0) {
+                    x = w;
+                } else {
+                    const uint32_t xb = sample_bits(p.areas, (size_t)b * MN + i);
+                    if (nonfinite_bits(xb)) atomicOr(flag, FOFSE_BLOCK_NONFINITE);
+                    else x = w * (double)__uint_as_float(xb);
+                }
+            }
+        }
+        const double* cr = cosm + m * kT + 16 * wv;       // C(16 wv + j, m), uniform
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = fma(cr[j], x, acc[j]);
+    }
+    if (col) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) buf[lane * kTP + 16 * wv + j] = acc[j];
+    }
+}
+
+// acc[j] = sum_{n < N} P[n][16 wv + j] C(l, n) for the lane's column l.
+__device__ __forceinline__ void row_pass(double (&acc)[16], const double* buf, int N,
+                                         const double* __restrict__ cosm, int wv, int lane) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int n = 0; n < N; ++n) {
+        const double c = cosm[n * kT + lane];
+        const double* pr = buf + n * kTP + 16 * wv;        // uniform: broadcast reads
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = fma(pr[j], c, acc[j]);
+    }
+}
+
+// Selection key of slot k: |R| with its 6 lowest mantissa bits replaced by
+// 63 - k (the magnitude changes by < 2^-46 relative); a larger key is a larger
+// magnitude, or the same magnitude in a smaller row.
+__device__ __forceinline__ double key_of(double r, int k) {
+    const uint32_t lo = ((uint32_t)__double2loint(r) & 0xFFFFFFC0u) | (uint32_t)(63 - k);
+    return __hiloint2double(__double2hiint(r), (int)lo);
+}
+
+// max(best, |key|) as one v_max_f64 with an absolute-value source modifier.
+__device__ __forceinline__ double max_abs(double best, double key) {
+    double r;
+    asm("v_max_f64 %0, |%1|, %2" : "=v"(r) : "v"(key), "v"(best));
+    return r;
+}
+
+// R of slot k (uniform) in lane `lane` (uniform), by a tree of uniform
+// branches down to a plain register read (a run-time register index would put
+// R in scratch memory).
+template <int LO, int HI>
+__device__ __forceinline__ double fetch_slot(const d16 (&R)[4], int k, int lane) {
+    if constexpr (HI - LO == 1) {
+        return readlane_f64(R[LO >> 4][LO & 15], lane);
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (k < MID) return fetch_slot<LO, MID>(R, k, lane);
+        return fetch_slot<MID, HI>(R, k, lane);
+    }
+}
+
+// The K iterations of one block held by this wavefront (R: slot k of chunk
+// k / 16 at element k % 16).  Writes the selection record of block b.
+__device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* tab, const KParams& p, int b, int lane,
+                                            double gamma) {
+    constexpr int T = kT;
+    const int K = p.K;
+    const double al = lane == 0 ? kA0 : kA1;
+    int u = 0, v = 0;
+    double q0 = 0.0, q1 = 0.0;          // update scale of row 0 and of rows 1..T-1 in this column
+    for (int it = 0;; ++it) {
+        // R[k][l] -= c <w phi_u, phi_{k,l}> for the 64 rows of column l = lane,
+        // then the key of each row.  Pass 0 runs with c = 0 (R unchanged).
+        const int cA = lane >= v ? lane - v : v - lane;
+        const int sb = lane + v;
+        const int cB = sb <= T ? sb : 2 * T - sb;
+        const double sB = sb <= T ? 1.0 : -1.0;
+        const double* pA = tab + cA;
+        const double* pB = tab + cB;
+        // the reads of slot k + kAhead are issued before slot k is computed
+        double t[kAhead][4];
+        auto load = [&](int k, double* x) {
+            const int rA = k >= u ? k - u : u - k;
+            const int rs = k + u;
+            const int rB = rs <= T ? rs : 2 * T - rs;
+            x[0] = pA[rA * kTP];
+            x[1] = pB[rA * kTP];
+            x[2] = pA[rB * kTP];
+            x[3] = pB[rB * kTP];
+        };
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) load(k, t[k]);
+        double best = 0.0;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+            const double sR = k + u <= T ? 1.0 : -1.0;
+            double* x = t[k % kAhead];
+            const double s = fma(sR, fma(sB, x[3], x[2]), fma(sB, x[1], x[0]));
+            if (k + kAhead < 64) load(k + kAhead, x);
+            const double r = fma(k == 0 ? -q0 : -q1, s, R[k >> 4][k & 15]);
+            R[k >> 4][k & 15] = r;
+            best = max_abs(best, key_of(r, k));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (it == K) break;
+
+        // eq. 9 over the wavefront: the largest high word, then among those the
+        // largest low word (magnitude bits and 63 - row), then the smallest lane
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        const uint32_t mlo = wave_max_u32(bhi == mhi ? blo : 0u);
+        const uint64_t hits = __ballot(bhi == mhi && blo == mlo);
+        const int vl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
+        const int uk = __builtin_amdgcn_readfirstlane(63 - (int)(mlo & 63u));
+        const double Ru = fetch_slot<0, 64>(R, uk, vl);
+
+        // eq. 5: <phi_u, phi_u>_w is the Gram entry at k = u (rows 0 and 2u,
+        // columns 0 and 2v); eq. 14: c = gamma p
+        const int d1 = 2 * uk, d2 = 2 * vl;
+        const int f1 = d1 <= T ? d1 : 2 * T - d1, f2 = d2 <= T ? d2 : 2 * T - d2;
+        const double s1 = d1 <= T ? 1.0 : -1.0, s2 = d2 <= T ? 1.0 : -1.0;
+        const double wsum = tab[0] + s2 * tab[f2] + s1 * (tab[f1 * kTP] + s2 * tab[f1 * kTP + f2]);
+        const double au1 = uk == 0 ? kA0 : kA1, au2 = vl == 0 ? kA0 : kA1;
+        const double S = 0.25 * (au1 * au1) * (au2 * au2) * wsum;
+        const double c = S > 0.0 ? gamma * Ru / S : 0.0;
+        if (lane == 0) {
+            const size_t r = (size_t)b * K + it;
+            p.sel[r] = uk * T + vl;
+            p.coef[2 * r] = c;
+            p.coef[2 * r + 1] = 0.0;
+        }
+        const double q = 0.25 * c * au1 * au2;
+        q0 = q * al * kA0;
+        q1 = q * al * kA1;
+        u = uk;
+        v = vl;
+    }
+}
+
+// g on B = sum_nu c_nu phi_{u_nu} from the record this wavefront wrote (read
+// back with cache-bypassing loads after the release fence); cs holds C(u, m)
+// at [m * T + u].
+__device__ __forceinline__ void dct_synthesis(const double* cs, const KParams& p, int b, int lane) {
+    const int K = p.K, N = p.N, nB = p.nB;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    const volatile int32_t* sel = p.sel + (size_t)b * K;
+    const volatile double* coef = p.coef + 2 * (size_t)b * K;
+    for (int q0 = 0; q0 < nB; q0 += 64) {
+        const int q = q0 + lane;
+        const bool ok = q < nB;
+        const int i = ok ? p.bpix[q] : 0;
+        const int m = i / N, n = i - m * N;
+        const double* cm = cs + m * kT;
+        const double* cn = cs + n * kT;
+        double acc = 0.0;
+        for (int nu0 = 0; nu0 < K; nu0 += 64) {
+            const int nu = nu0 + lane;
+            int key = 0;
+            double c = 0.0;
+            if (nu < K) {
+                key = sel[nu];
+                c = coef[2 * nu];
+            }
+            const int cnt = K - nu0 < 64 ? K - nu0 : 64;
+            for (int j = 0; j < cnt; ++j) {
+                const int kj = __builtin_amdgcn_readlane(key, j);
+                const double cj = readlane_f64(c, j);
+                const int u1 = (kj >> 6) & 63, u2 = kj & 63;
+                const double s = cj * (u1 == 0 ? kA0 : kA1) * (u2 == 0 ? kA0 : kA1);
+                acc = fma(s, cm[u1] * cn[u2], acc);
+            }
+        }
+        if (ok) p.out[(size_t)b * nB + q] = (float)acc;
+    }
+}
+
+// One work item: up to kGroup blocks of one support mask.
+__device__ __forceinline__ void dct_item(DctShared& sh, const KParams& p, const GroupArgs& g,
+                                         const double* __restrict__ cosm, int item, int tid, int lane,
+                                         int wv, bool params_ok, double gamma) {
+    const int M = p.M, N = p.N, MN = M * N, K = p.K;
+    int nblk, blk[kGroup];
+    if (g.direct) {
+        nblk = min(kGroup, p.n_blocks - item * kGroup);
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) blk[j] = item * kGroup + j;
+    } else {
+        nblk = g.item_n[item];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) blk[j] = g.item_blk[(size_t)item * kGroup + j];
+    }
+    const size_t rep_base = (size_t)blk[0] * MN;    // every block of the item has this mask
+    __syncthreads();                                 // the previous item is done with the LDS
+    if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    __syncthreads();
+    (void)M;
+
+    d16 R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) R[c] = (d16)0.0;
+    if (params_ok) {
+        // R = DCT(w f) of each block (eqs. 7, 8), staged in the table's space
+        const double al = lane == 0 ? kA0 : kA1;
+        for (int j = 0; j < kGroup; ++j) {
+            if (j >= nblk) break;                    // uniform over the workgroup
+            column_pass(sh.buf, p, g, rep_base, blk[j], &sh.flags[j], cosm, wv, lane);
+            __syncthreads();
+            double acc[16];
+            row_pass(acc, sh.buf, N, cosm, wv, lane);
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int k = 16 * wv + jj;
+                sh.tab[k * kT + lane] = acc[jj] * al * (k == 0 ? kA0 : kA1);
+            }
+            __syncthreads();
+            if (wv == j) {
+#pragma unroll
+                for (int k = 0; k < 64; ++k) R[k >> 4][k & 15] = sh.tab[k * kT + lane];
+            }
+        }
+        // the table Wc of the item's w; the last block's reads of the staging
+        // finish before the barrier that precedes the table writes
+        column_pass(sh.buf, p, g, rep_base, -1, nullptr, cosm, wv, lane);
+        __syncthreads();
+        double acc[16];
+        row_pass(acc, sh.buf, N, cosm, wv, lane);
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) sh.tab[(16 * wv + jj) * kTP + lane] = acc[jj];
+        if (tid < kTP) sh.tab[kT * kTP + tid] = 0.0;
+        if (tid < kT) sh.tab[tid * kTP + kT] = 0.0;
+        __syncthreads();
+        // cosine table for the synthesis, over the column pass's space
+        for (int i = tid; i < kT * kT; i += kNT) sh.buf[i] = cosm[i];
+        __syncthreads();
+    }
+
+    const bool present = wv < nblk;
+    int flags = present ? sh.flags[wv] : 0;
+    const double W0 = params_ok ? sh.tab[0] : 0.0;   // Wc[0][0] = sum of the weights
+    if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
+    const bool live = present && flags == 0;
+    const int bj = blk[wv < kGroup ? wv : 0];
+    if (live) {
+        dct_iterate(R, sh.tab, p, bj, lane, gamma);
+        dct_synthesis(sh.buf, p, bj, lane);
+    } else if (present) {                            // empty record, model 0
+        for (int it = lane; it < K; it += 64) {
+            const size_t r = (size_t)bj * K + it;
+            p.sel[r] = 0;
+            p.coef[2 * r] = 0.0;
+            p.coef[2 * r + 1] = 0.0;
+        }
+        for (int q = lane; q < p.nB; q += 64) p.out[(size_t)bj * p.nB + q] = 0.0f;
+    }
+    if (present && lane == 0 && p.status) p.status[bj] = flags;
+}
+
+__global__ __launch_bounds__(kNT, 2) void fofse_dct_kernel(KParams p, GroupArgs g,
+                                                            const double* __restrict__ cosm) {
+    __shared__ DctShared sh;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x(), lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
+    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    // items of this workgroup: a contiguous range
+    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
+    const int per = (n_items + g.n_wg - 1) / g.n_wg;
+    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+    const int i1 = min(n_items, i0 + per);
+    for (int item = i0; item < i1; ++item) dct_item(sh, p, g, cosm, item, tid, lane, wv, params_ok, gamma);
+}
+
+}  // namespace
+
+hipError_t launch_dct(const KParams& p, const GroupArgs& g, const double* cosm, int n_cu, hipStream_t stream,
+                      const Timing& tm) {
+    if (p.T != kDctT || p.M > kDctT || p.N > kDctT || !cosm) return hipErrorInvalidValue;
+    const hipError_t ew = launch_weights(p, stream);
+    if (ew != hipSuccess) return ew;
+    GroupArgs ga = g;
+    ga.gsize = kGroup;
+    ga.gshift = kGroupShift;
+    if (!g.direct) {
+        const hipError_t eg = launch_grouping(ga, p.n_blocks, stream);
+        if (eg != hipSuccess) return eg;
+    }
+    const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
+    int grid = 2 * n_cu;
+    if (grid > max_items) grid = max_items;
+    ga.n_wg = grid;
+    if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
+    hipLaunchKernelGGL(fofse_dct_kernel, dim3(grid), dim3(kNT), 0, stream, p, ga, cosm);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
+    return hipSuccess;
+}
+
+}  // namespace fofse

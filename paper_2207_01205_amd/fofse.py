@@ -31,7 +31,11 @@ FOFSE_PATH_AUTO = 0
 FOFSE_PATH_SPLIT = 1
 FOFSE_PATH_GROUPED = 2
 
+FOFSE_BASIS_DFT = 0
+FOFSE_BASIS_DCT = 1
+
 EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves",
+            "fofse_set_basis",
             "fofse_extrapolate_batch",
             "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
             "fofse_status_str")
@@ -72,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_set_path.restype = ctypes.c_int
     L.fofse_set_waves.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_waves.restype = ctypes.c_int
+    L.fofse_set_basis.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_basis.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
     L.fofse_backward.argtypes = [vp, ctypes.c_int32] + [vp] * 10
@@ -124,6 +130,12 @@ def fofse_set_waves(plan: int, waves: int) -> None:
     st = load_library().fofse_set_waves(plan, int(waves))
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_set_waves")
+
+
+def fofse_set_basis(plan: int, basis: int) -> None:
+    st = load_library().fofse_set_basis(plan, int(basis))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_basis")
 
 
 def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int,
@@ -187,6 +199,11 @@ class Plan:
 
     def set_waves(self, waves: int):
         fofse_set_waves(self.handle, waves)
+
+    def set_basis(self, basis: int):
+        """FOFSE_BASIS_DFT (default) or FOFSE_BASIS_DCT; with the DCT the
+        record holds keys k*T + l in [0, T*T) and real coefficients (c, 0)."""
+        fofse_set_basis(self.handle, basis)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1,0 +1,185 @@
+"""Parity of the DCT-basis path (fofse_set_basis(FOFSE_BASIS_DCT), through the
+C ABI) with the FP64 DCT oracle.
+
+Acceptance rule, as for the DFT basis: the selected keys k*T + l equal the
+oracle's on every iteration before the first whose oracle margin is <= 1e-6
+(relative, on |R|) or whose gap between the two largest magnitudes is at the
+FP64 rounding level of the residual; blocks whose sequences match have
+max |g_gpu - g_oracle| <= 1e-3 on the 0..255 scale and coefficients within
+1e-9 of the largest |c| of the block.  Blocks that diverge at or after that
+iteration are counted and reported, not failed.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.fofse_dct import fofse_dct
+from oracle.fofse_dft import selection_parity
+from paper_2207_01205_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL_G = 1e-3
+MARGIN = 1e-6
+
+
+def _plan(M, N, K, target, T=64):
+    from paper_2207_01205_amd.fofse import FOFSE_BASIS_DCT, Plan
+    plan = Plan(M, N, T, K, target, device=0)
+    plan.set_basis(FOFSE_BASIS_DCT)
+    return plan
+
+
+def run_gpu(plan, areas, known, rho, gamma, label):
+    print(f"[gpu] DCT {label}: n={areas.shape[0]} M={plan.M} N={plan.N} T={plan.T} K={plan.K}",
+          flush=True)
+    dev = torch.device("cuda", 0)
+    a = torch.from_numpy(np.ascontiguousarray(areas, dtype=np.float32)).to(dev)
+    k = None if known is None else torch.from_numpy(np.ascontiguousarray(known, dtype=np.uint8)).to(dev)
+    rg = torch.tensor([rho, gamma], dtype=torch.float64, device=dev)
+    out, sel, coef, st = plan.extrapolate(a, rg, known=k, record=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), sel.cpu().numpy(), coef.cpu().numpy(), st.cpu().numpy()
+
+
+def oracle_on(areas, known, target, T, rho, gamma, K):
+    f = np.asarray(areas, dtype=np.float32).astype(np.float64)   # the exact inputs the GPU sees
+    kn = (np.broadcast_to(1 - target, f.shape) if known is None else known).astype(np.uint8)
+    kn = kn * (1 - target)[None]
+    return fofse_dct(np.where(kn != 0, f, 0.0), kn, T, rho, gamma, K)   # samples off A are ignored
+
+
+def check_parity(ref, target, out, sel, coef, st, label):
+    assert np.all(st == 0), f"{label}: unexpected block status {np.unique(st)}"
+    assert np.all((sel >= 0) & (sel < 64 * 64))
+    assert np.all(coef[..., 1] == 0.0)
+    ok, div = selection_parity(sel, ref.keys, ref.margin, MARGIN, top_ref=ref.top)
+    bad = np.nonzero(~ok)[0]
+    assert len(bad) == 0, f"{label}: selection differs before the margin rule allows, blocks {bad[:10]}"
+    same = np.all(sel == ref.keys, axis=1)
+    tb = target.reshape(-1) == 1
+    g_ref = ref.g.reshape(ref.g.shape[0], -1)[:, tb]
+    err = np.abs(out - g_ref).max(axis=1)
+    assert np.all(err[same] <= TOL_G), f"{label}: max |dg| {err[same].max()}"
+    if same.any():
+        scale = np.maximum(np.abs(ref.coef[same]).max(axis=1, keepdims=True), 1e-300)
+        cerr = np.abs(coef[same][..., 0] - ref.coef[same]) / scale
+        assert cerr.max() <= 1e-9, f"{label}: coefficient error {cerr.max():.3e}"
+    print(f"[gpu] DCT {label}: blocks={len(same)} diverging={int(div.sum())} "
+          f"max|dg|={err[same].max() if same.any() else 0:.3e}", flush=True)
+    return same
+
+
+@pytest.fixture(scope="module")
+def frame_areas():
+    return synth.frame_concealment(0, 1)
+
+
+def test_dct_frame_blocks(frame_areas):
+    """48 frame blocks (48 x 48 areas, 16 x 16 losses, K = 200): per-block masks
+    with classes of several blocks and singletons."""
+    A = frame_areas
+    sub = slice(300, 348)
+    plan = _plan(48, 48, 200, A.target)
+    out, sel, coef, st = run_gpu(plan, A.areas[sub], A.known[sub], 0.8, 0.5, "frame blocks 300-347")
+    ref = oracle_on(A.areas[sub], A.known[sub], A.target, 64, 0.8, 0.5, 200)
+    same = check_parity(ref, A.target, out, sel, coef, st, "frame blocks")
+    assert same.sum() >= len(same) - 3
+
+
+@pytest.mark.parametrize("M,N,K,n", [(48, 48, 1, 5), (40, 44, 65, 9), (64, 64, 120, 6), (17, 33, 300, 7)])
+def test_dct_canonical_mask(M, N, K, n):
+    """No known-mask array (every block's support is the complement of B):
+    ragged batches (items of four blocks and a remainder), areas up to the grid."""
+    rng = np.random.default_rng(M * N + K)
+    target = np.zeros((M, N), np.uint8)
+    target[M // 2 - M // 6:M // 2 + M // 6, N // 2 - N // 5:N // 2 + N // 5] = 1
+    m = np.arange(M)[:, None]
+    nn = np.arange(N)[None, :]
+    base = 120 + 50 * np.cos(2 * np.pi * (0.05 * m + 0.12 * nn)) + 25 * np.sin(2 * np.pi * 0.19 * m)
+    areas = (base[None] + 6 * rng.normal(size=(n, M, N))).astype(np.float32)
+    plan = _plan(M, N, K, target)
+    out, sel, coef, st = run_gpu(plan, areas, None, 0.85, 0.4, f"canonical {M}x{N} K={K}")
+    ref = oracle_on(areas, None, target, 64, 0.85, 0.4, K)
+    same = check_parity(ref, target, out, sel, coef, st, f"canonical {M}x{N} K={K}")
+    assert same.sum() >= n - 1
+
+
+def test_dct_edge_cases(frame_areas):
+    A = frame_areas
+    sub = slice(0, 10)
+    areas = A.areas[sub].copy()
+    known = A.known[sub].copy()
+    areas[2, 0, 0] = np.nan            # non-finite known sample
+    known[2, 0, 0] = 1
+    known[5] = 0                       # no support at all
+    areas[6, 20, 20] = np.inf          # on B: ignored
+    areas[7] = 0.0                     # R = 0 everywhere: key 0 with c = 0 every time
+    plan = _plan(48, 48, 40, A.target)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, "edge cases")
+    from paper_2207_01205_amd.fofse import FOFSE_BLOCK_NONFINITE, FOFSE_BLOCK_NO_SUPPORT
+    assert st[2] == FOFSE_BLOCK_NONFINITE and st[5] == FOFSE_BLOCK_NO_SUPPORT
+    for b in (2, 5):
+        assert np.all(out[b] == 0) and np.all(sel[b] == 0) and np.all(coef[b] == 0)
+    assert np.all(sel[7] == 0) and np.all(coef[7] == 0) and np.all(out[7] == 0)
+    ok = [0, 1, 3, 4, 6, 7, 8, 9]
+    ref = oracle_on(areas[ok], known[ok], A.target, 64, 0.8, 0.5, 40)
+    check_parity(ref, A.target, out[ok], sel[ok], coef[ok], st[ok], "edge cases (regular blocks)")
+    # parameters out of range: every block flagged, outputs zero
+    from paper_2207_01205_amd.fofse import FOFSE_BLOCK_BAD_PARAM
+    out2, sel2, coef2, st2 = run_gpu(plan, areas, known, 0.8, 0.0, "gamma 0")
+    assert np.all(st2 == FOFSE_BLOCK_BAD_PARAM) and np.all(out2 == 0) and np.all(coef2 == 0)
+    # K = 0: the model is 0
+    plan0 = _plan(48, 48, 0, A.target)
+    out3, _, _, st3 = run_gpu(plan0, A.areas[sub], A.known[sub], 0.8, 0.5, "K = 0")
+    assert np.all(st3 == 0) and np.all(out3 == 0)
+
+
+def test_dct_block_result_does_not_depend_on_the_batch(frame_areas):
+    """The same blocks alone and inside a larger batch (other work-item
+    partners, other workgroups) give the same bits; repeated calls too."""
+    A = frame_areas
+    plan = _plan(48, 48, 100, A.target)
+    full = run_gpu(plan, A.areas[:200], A.known[:200], 0.8, 0.5, "batch of 200")
+    again = run_gpu(plan, A.areas[:200], A.known[:200], 0.8, 0.5, "batch of 200, repeated")
+    part = run_gpu(plan, A.areas[37:61], A.known[37:61], 0.8, 0.5, "blocks 37-60 alone")
+    for x, y in zip(full, again):
+        assert np.array_equal(x, y)
+    for x, y in zip(full, part):
+        assert np.array_equal(x[37:61], y)
+
+
+def test_dct_full_size_sampled():
+    """The throughput workload (16 frames, 12,864 blocks, K = 200) in one call:
+    every block processed, valid records, and 48 sampled blocks against the
+    oracle."""
+    A = synth.replicate_frames(16, 0, 1000)
+    n = A.areas.shape[0]
+    plan = _plan(48, 48, 200, A.target)
+    out, sel, coef, st = run_gpu(plan, A.areas, A.known, 0.8, 0.5, f"16 frames, {n} blocks")
+    assert np.all(st == 0) and np.all(np.isfinite(out))
+    pick = np.sort(np.random.default_rng(5).choice(n, 48, replace=False))
+    ref = oracle_on(A.areas[pick], A.known[pick], A.target, 64, 0.8, 0.5, 200)
+    same = check_parity(ref, A.target, out[pick], sel[pick], coef[pick], st[pick], "16 frames, sampled")
+    assert same.sum() >= len(pick) - 3
+
+
+def test_dct_unsupported_configurations():
+    from paper_2207_01205_amd.fofse import FOFSE_BASIS_DCT, FOFSE_ERR_UNSUPPORTED, FofseError, Plan
+    target = np.zeros((16, 16), np.uint8)
+    target[6:10, 6:10] = 1
+    p32 = Plan(16, 16, 32, 10, target, device=0)
+    with pytest.raises(FofseError) as e:
+        p32.set_basis(FOFSE_BASIS_DCT)
+    assert e.value.status == FOFSE_ERR_UNSUPPORTED
+    plan = _plan(16, 16, 10, target)
+    dev = torch.device("cuda", 0)
+    a = torch.zeros((2, 16, 16), dtype=torch.float32, device=dev)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    sel = torch.zeros((2, 10), dtype=torch.int32, device=dev)
+    coef = torch.zeros((2, 10, 2), dtype=torch.float64, device=dev)
+    go = torch.zeros((2, plan.nB), dtype=torch.float32, device=dev)
+    with pytest.raises(FofseError) as e:
+        plan.backward(a, rg, sel, coef, go)
+    assert e.value.status == FOFSE_ERR_UNSUPPORTED
