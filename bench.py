@@ -7,8 +7,8 @@ Workload: 1080p frame concealment (the paper's block-loss concealment setting:
 of the 120 x 67 full macroblocks lost (804 blocks per frame).  One step = one
 forward pass over a batch of ``--frames`` frames, inputs resident in HBM; the
 forward+adjoint step adds the MSE gradient on B against the true pixels and the
-adjoint pass (gradients for the known samples, rho_hat and gamma).  Prints one
-JSON line.
+adjoint pass (gradients for the known samples, rho_hat and gamma); the DCT leg
+runs the same batch with DCT basis functions.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
 """
@@ -73,6 +73,14 @@ def adjoint_flops_per_block(T: int, K: int, nB: int) -> float:
     complex multiply-adds, 16, and the two rho_hat terms, 20), and two T x T
     FFTs (weights with their rho_hat derivative, and the adjoint spectrum)."""
     return 4.0 * K * nB + 36.0 * K * (K - 1) / 2 + 2 * 2.5 * T * T * np.log2(T * T)
+
+
+def dct_flops_per_block(T: int, K: int) -> float:
+    """Algorithmic FLOP of one block with DCT basis functions: per iteration 6
+    per bin over the T^2 bins (the four-entry Gram sum: 3, the scaled
+    subtraction: 2, the magnitude comparison: 1), plus two T x T transforms at
+    2.5 T^2 log2(T^2) each (forward transform, synthesis)."""
+    return K * 6.0 * T * T + 2 * 2.5 * T * T * np.log2(T * T)
 
 
 def adjoint_kernel_name(n: int, dev) -> str:
@@ -177,6 +185,83 @@ def cpu_baseline(areas, known, target, n_sample: int, workers: int):
         "cpu_model": _cpu_model(),
     }
     return info, (idx, g, keys, margin, top)
+
+
+DCT_SAMPLE = 64        # oracle-checked blocks of the DCT-basis leg
+
+
+def _dct_oracle_chunk(args):
+    areas, known, target = args
+    from oracle.fofse_dct import fofse_dct
+    f = areas.astype(np.float32).astype(np.float64)
+    kn = known * (1 - target)[None]
+    r = fofse_dct(np.where(kn != 0, f, 0.0), kn, T, RHO, GAMMA, K)
+    return r.g.reshape(len(f), -1)[:, target.reshape(-1) == 1], r.keys, r.margin, r.top
+
+
+def dct_cpu_baseline(areas, known, target, n_sample: int, workers: int):
+    """The FP64 DCT-basis oracle, unchanged, on a seeded sample of the batch's
+    blocks (timed, and the parity reference of the DCT leg).  Runs before the
+    GPU is touched."""
+    idx = np.sort(np.random.default_rng(12).choice(len(areas), n_sample, replace=False))
+    chunks = [c for c in np.array_split(idx, workers) if len(c)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(chunks)) as pool:
+        res = pool.map(_dct_oracle_chunk, [(areas[c], known[c], target) for c in chunks])
+    dt = time.perf_counter() - t0
+    info = {"value": n_sample / dt, "unit": "blocks/s", "cores": len(chunks), "kind": "oracle",
+            "sample": f"{n_sample} seeded blocks of the same batch (FP64 NumPy DCT oracle, "
+                      f"{len(chunks)} processes, {dt:.1f} s)"}
+    ref = (idx,) + tuple(np.concatenate([r[i] for r in res]) for i in range(4))
+    return info, ref
+
+
+def run_dct(d_areas, d_known, target, n, args, dev, base):
+    """The same batch with DCT basis functions: K steps of one forward launch."""
+    import torch
+    from paper_2207_01205_amd import fofse as F
+    plan = F.Plan(AREA, AREA, T, K, target, device=0)
+    plan.set_basis(F.FOFSE_BASIS_DCT)
+    out = torch.empty((n, plan.nB), dtype=torch.float32, device=dev)
+    sel = torch.empty((n, K), dtype=torch.int32, device=dev)
+    coef = torch.empty((n, K, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        F.fofse_extrapolate_batch(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(),
+                                  rg.data_ptr(), out.data_ptr(), sel.data_ptr(),
+                                  coef.data_ptr(), st.data_ptr(), stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.fofse_set_timing(plan.handle, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        step()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    kern = float(np.mean(F.fofse_kernel_times(plan.handle, args.steps))) * 1e-3
+    F.fofse_set_timing(plan.handle, False)
+    total = ev[0].elapsed_time(ev[1]) * 1e-3
+    fpb = dct_flops_per_block(T, K)
+    res = {"value": n * args.steps / total, "unit": "blocks/s", "ms_per_step": total / args.steps * 1e3,
+           "roofline": {"bound": "alu", "kernel": "fofse_dct_kernel", "flop_per_block": fpb,
+                        "avg_launch_ms": kern * 1e3, "achieved": fpb * n / kern / 1e12,
+                        "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                        "frac": fpb * n / kern / FP64_VECTOR_PEAK},
+           "block_status_nonzero": int(np.count_nonzero(st.cpu().numpy()))}
+    print(f"[bench] DCT basis: {total / args.steps * 1e3:.3f} ms per step, kernel {kern * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    if base is not None:
+        info, ref = base
+        info["sample_parity"] = sample_parity(ref, out.cpu().numpy(), sel.cpu().numpy())
+        res["cpu_baseline"] = info
+    plan.close()
+    return res
 
 
 def sample_parity(ref, gpu_out, gpu_sel):
@@ -408,6 +493,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--no-dct", action="store_true", help="skip the DCT-basis leg")
     ap.add_argument("--mixed", type=int, default=25000, metavar="PER_CLASS",
                     help="blocks per size class of the mixed-size batch (0 = skip)")
     ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
@@ -451,6 +537,10 @@ def main():
         base = cpu_baseline(areas, known, target, min(args.cpu_sample, n), workers)
         print(f"[bench] cpu baseline: {base[0]['value']:.2f} blocks/s on {workers} processes",
               file=sys.stderr, flush=True)
+    dct_base = None
+    if not args.no_cpu_baseline and not args.no_dct:
+        dct_base = dct_cpu_baseline(areas, known, target, min(DCT_SAMPLE, n),
+                                    min(16, len(os.sched_getaffinity(0))))
 
     import torch
     from paper_2207_01205_amd.fofse import Plan
@@ -596,6 +686,7 @@ def main():
         adj["graph_ms_per_step"] = t_g / args.steps * 1e3
         del graph
 
+    dct = None if args.no_dct else run_dct(d_areas, d_known, target, n, args, dev, dct_base)
     tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
     mixed = run_mixed(mixed_data, mixed_ref, args, dev) if mixed_data is not None else None
 
@@ -639,6 +730,7 @@ def main():
                      "avg_launch_ms": kern * 1e3, "avg_step_ms": float(np.mean(per_step)) * 1e3},
         "block_status_nonzero": int(np.count_nonzero(status)),
         "fwd_adjoint": adj,
+        "dct_basis": dct,
     }
     if tuning is not None:
         result["tuning"] = tuning
