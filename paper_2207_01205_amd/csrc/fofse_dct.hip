@@ -268,7 +268,6 @@ __device__ __forceinline__ void dct_item(DctShared& sh, const KParams& p, const 
     __syncthreads();                                 // the previous item is done with the LDS
     if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
-    (void)M;
 
     d16 R[4];
 #pragma unroll
