@@ -9,9 +9,11 @@
 // Grouping runs on the device:
 //   k_mask_hash   64-bit hash of each block's mask, inserted into an open-address
 //                 table (the first inserter becomes the class representative)
-//   k_group_count exact byte comparison with the representative; position of
-//                 the block inside its class (blocks that differ from their
-//                 representative on a hash collision become singletons)
+//   k_group_count exact byte comparison with the representative (blocks that
+//                 differ from their representative on a hash collision become
+//                 singletons)
+//   k_group_pos   position of each block inside its class (one atomic per
+//                 distinct class of a wavefront of blocks)
 //   k_group_scan  work items per class (ceil(count / gsize)) -> item offsets
 //   k_group_fill  item -> list of its blocks
 // The main kernel is persistent: workgroup g processes a contiguous range of
@@ -87,9 +89,17 @@ __global__ __launch_bounds__(64 * kHashBlocks) void k_mask_hash(GroupArgs g, int
     if (lane == 0) {
         uint32_t slot = (uint32_t)(h >> 17) & g.hmask;
         for (;;) {
-            const unsigned long long prev = atomicCAS(&g.ht_key[slot], 0ull, (unsigned long long)h);
-            if (prev == 0ull) { g.ht_rep[slot] = b; break; }
-            if (prev == h) break;
+            // most blocks find their class already inserted: a plain read first
+            // keeps them off the atomic unit (a stale 0 just falls through to the
+            // compare-and-swap, which decides)
+            const unsigned long long seen =
+                __hip_atomic_load(&g.ht_key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (seen == h) break;
+            if (seen == 0ull) {
+                const unsigned long long prev = atomicCAS(&g.ht_key[slot], 0ull, (unsigned long long)h);
+                if (prev == 0ull) { g.ht_rep[slot] = b; break; }
+                if (prev == h) break;
+            }
             slot = (slot + 1) & g.hmask;
         }
         g.cls[b] = (int)slot;
@@ -117,40 +127,74 @@ __global__ __launch_bounds__(64 * kHashBlocks) void k_group_count(GroupArgs g, i
             same = same && (eff_known(g.known, g.target, base, i) == eff_known(g.known, g.target, rbase, i));
     }
     same = __all(same);
-    if (lane == 0) {
-        if (same) {
-            g.pos[b] = atomicAdd(&g.ht_cnt[slot], 1);
-        } else {
-            g.pos[b] = atomicAdd(g.n_single, 1);
-            g.cls[b] = -1;
-        }
+    if (lane == 0 && !same) g.cls[b] = -1;
+}
+
+// One thread per block: its position inside its class (or among the
+// singletons).  The lanes of a wavefront that share a class take consecutive
+// positions from one atomic add.
+__global__ __launch_bounds__(256) void k_group_pos(GroupArgs g, int n) {
+    const int b = (int)__builtin_amdgcn_workgroup_id_x() * 256 + (int)__builtin_amdgcn_workitem_id_x();
+    const int lane = (int)__builtin_amdgcn_workitem_id_x() & 63;
+    const bool valid = b < n;
+    const int slot = valid ? g.cls[b] : 0;
+    uint64_t todo = __ballot(valid);
+    int pos = 0;
+    while (todo) {
+        const int leader = (int)__builtin_ctzll(todo);
+        const int s = __builtin_amdgcn_readlane(slot, leader);
+        const uint64_t m = __ballot(valid && slot == s);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(s >= 0 ? &g.ht_cnt[s] : g.n_single, (int)__popcll(m));
+        base = __builtin_amdgcn_readlane(base, leader);
+        if (valid && slot == s) pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
     }
+    if (valid) g.pos[b] = pos;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 // One workgroup of 1024 threads: items per slot and their exclusive prefix.
+// Wave w owns the slots [w P, (w + 1) P), P = hsize / 16 (hsize is a power of
+// two >= 64), read 64 at a time (coalesced): a first pass sums them, the wave
+// offsets follow from the 16 sums, a second pass scans each group of 64.
 __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
-    __shared__ int part[1024];
-    const int tid = (int)__builtin_amdgcn_workitem_id_x();
-    const int per = (g.hsize + 1023) / 1024;
-    const int s0 = tid * per;
-    int sum = 0;
-    for (int s = s0; s < s0 + per && s < g.hsize; ++s) sum += (g.ht_cnt[s] + g.gsize - 1) >> g.gshift;
-    part[tid] = sum;
+    __shared__ int wtot[16];
+    const int tid = (int)__builtin_amdgcn_workitem_id_x(), lane = tid & 63, w = tid >> 6;
+    const int P = g.hsize >> 4;
+    const int start = w * P, end = start + P;
+    int tot = 0;
+#pragma unroll 4
+    for (int c = start + lane; c < end; c += 64) tot += (g.ht_cnt[c] + g.gsize - 1) >> g.gshift;
+    tot = wave_sum_i32(tot);
+    if (lane == 0) wtot[w] = tot;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {       // inclusive scan (Hillis-Steele)
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    int carry = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        carry += i < w ? wtot[i] : 0;
+        all += wtot[i];
     }
-    int run = part[tid] - sum;
-    for (int s = s0; s < s0 + per && s < g.hsize; ++s) {
-        g.item_start[s] = run;
-        run += (g.ht_cnt[s] + g.gsize - 1) >> g.gshift;
+    for (int c0 = start; c0 < end; c0 += 64) {
+        const int c = c0 + lane;
+        const int x = c < end ? (g.ht_cnt[c] + g.gsize - 1) >> g.gshift : 0;
+        int incl = x;                                 // inclusive scan over the wavefront
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            incl += lane >= off ? y : 0;
+        }
+        if (c < end) g.item_start[c] = carry + incl - x;
+        carry += __builtin_amdgcn_readlane(incl, 63);
     }
-    if (tid == 1023) {
-        g.counts[0] = part[1023];                    // grouped items
-        g.counts[1] = part[1023] + *g.n_single;      // all items
+    if (tid == 0) {
+        g.counts[0] = all;                            // grouped items
+        g.counts[1] = all + *g.n_single;              // all items
     }
 }
 
@@ -414,6 +458,7 @@ hipError_t launch_grouping(const GroupArgs& g, int n, hipStream_t stream) {
     const int nwg = (n + kHashBlocks - 1) / kHashBlocks;
     hipLaunchKernelGGL(k_mask_hash, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
     hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(64 * kHashBlocks), 0, stream, g, n);
+    hipLaunchKernelGGL(k_group_pos, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
     hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, stream, g);
     hipLaunchKernelGGL(k_group_fill, dim3((n + 255) / 256), dim3(256), 0, stream, g, n);
     return hipGetLastError();
