@@ -245,3 +245,21 @@ def test_deterministic(frame_areas, path):
     r2 = run_gpu(plan, A.areas[:64], A.known[:64], 0.8, 0.5, f"determinism run 2 {path}")
     for x, y in zip(r1, r2):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("T", [64, 128])
+def test_grouped_result_does_not_depend_on_the_batch(T):
+    """Grouped forward: the same blocks alone and inside a larger batch (other
+    work-item partners, another order inside each mask class, other
+    workgroups) give the same bits."""
+    A = synth.frame_concealment(5, 6)
+    plan = _plan(48, 48, T, 120, A.target, "grouped")
+    full = run_gpu(plan, A.areas[:300], A.known[:300], 0.8, 0.5, f"T={T} batch of 300")
+    part = run_gpu(plan, A.areas[101:131], A.known[101:131], 0.8, 0.5, f"T={T} blocks 101-130 alone")
+    shuffled = np.random.default_rng(1).permutation(300)
+    mixed = run_gpu(plan, A.areas[shuffled], A.known[shuffled], 0.8, 0.5, f"T={T} batch of 300, shuffled")
+    for x, y in zip(full, part):
+        assert np.array_equal(x[101:131], y)
+    inv = np.argsort(shuffled)
+    for x, y in zip(full, mixed):
+        assert np.array_equal(x, y[inv])
