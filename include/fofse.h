@@ -190,7 +190,8 @@ fofse_status fofse_set_waves(fofse_plan plan, int32_t waves);
  * Profiling hook.  With timing enabled, every fofse_extrapolate_batch and
  * fofse_backward call records a pair of HIP events on its stream around its
  * main kernel (the iteration kernel, or the adjoint kernel; the weight,
- * grouping, synthesis and summation kernels are outside).
+ * grouping, synthesis and summation kernels are outside; with the DCT basis
+ * the one kernel iterates and synthesises).
  * The plan keeps the pairs of the last 256 calls.
  *   fofse_set_timing    enable (non-zero) or disable; enabling clears the ring.
  *                       FOFSE_ERR_ARG for a NULL plan, FOFSE_ERR_DEVICE if the
