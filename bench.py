@@ -8,7 +8,9 @@ of the 120 x 67 full macroblocks lost (804 blocks per frame).  One step = one
 forward pass over a batch of ``--frames`` frames, inputs resident in HBM; the
 forward+adjoint step adds the MSE gradient on B against the true pixels and the
 adjoint pass (gradients for the known samples, rho_hat and gamma); the DCT leg
-runs the same batch with DCT basis functions.  Prints one JSON line.
+runs the same batch with DCT basis functions, and the full-compensation leg
+with the orthogonality deficiency compensation of eqs. 10-13 (OFSE).  Prints
+one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
 """
@@ -35,13 +37,13 @@ FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
 # HBM traffic of the main forward kernel per launch on the 16-frame batch,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
 # of ``bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame
-# --no-adjoint --mixed 0 --no-dct --copy-calibration 256 --jobs 1``.  In those runs a plain 256 MiB device copy read
+# --no-adjoint --mixed 0 --no-dct --no-ofse --copy-calibration 256 --jobs 1``.  In those runs a plain 256 MiB device copy read
 # FETCH_SIZE = 131,094 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is scaled
 # by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel sources it
 # was taken on (hash below); otherwise the bench reports null.
 KERNEL_SOURCES = ("fofse_group.hip", "iterate.hpp", "device_common.hpp", "fofse_kernel.h")
-TRAFFIC = {"sources_sha256_16": "29ef88be6339cbc4", "blocks": 12864,
-           "fetch_kib": 91423.0, "write_kib": 67621.7, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "6bc39de9aadf55e7", "blocks": 12864,
+           "fetch_kib": 91470.8, "write_kib": 67624.1, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def measured_traffic(n_blocks: int):
@@ -255,6 +257,95 @@ def run_dct(d_areas, d_known, target, n, args, dev, base):
                         "frac": fpb * n / kern / FP64_VECTOR_PEAK},
            "block_status_nonzero": int(np.count_nonzero(st.cpu().numpy()))}
     print(f"[bench] DCT basis: {total / args.steps * 1e3:.3f} ms per step, kernel {kern * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    if base is not None:
+        info, ref = base
+        info["sample_parity"] = sample_parity(ref, out.cpu().numpy(), sel.cpu().numpy())
+        res["cpu_baseline"] = info
+    plan.close()
+    return res
+
+
+OFSE_SAMPLE = 32       # oracle-checked blocks of the full-compensation leg
+
+
+def ofse_flops_per_block(T: int, K: int) -> float:
+    """Algorithmic FLOP of one block with the full compensation of eqs. 10-13:
+    the FOFSE iteration plus, per iteration, the convolution (R (*) W)[u] over
+    the full spectrum (two complex multiply-adds, 16 FLOP, per conjugate
+    class)."""
+    return flops_per_block(T, K) + K * 16.0 * (T * T // 2 + 2)
+
+
+def _ofse_oracle_chunk(args):
+    areas, known, target = args
+    from oracle.ofse_dft import ofse_full
+    kn = known * (1 - target)[None]
+    out = []
+    for b in range(len(areas)):
+        f = areas[b].astype(np.float32).astype(np.float64)
+        r = ofse_full(np.where(kn[b] != 0, f, 0.0), kn[b], T, RHO, K)
+        out.append((r["g"].reshape(-1)[target.reshape(-1) == 1], r["keys"], r["margin"], r["top"]))
+    return out
+
+
+def ofse_cpu_baseline(areas, known, target, n_sample: int, workers: int):
+    """The FP64 OFSE oracle (eqs. 10-13 in the DFT domain), unchanged, on a
+    seeded sample of the batch's blocks (timed, and the parity reference of the
+    full-compensation leg).  Runs before the GPU is touched."""
+    idx = np.sort(np.random.default_rng(13).choice(len(areas), n_sample, replace=False))
+    chunks = [c for c in np.array_split(idx, workers) if len(c)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(chunks)) as pool:
+        res = pool.map(_ofse_oracle_chunk, [(areas[c], known[c], target) for c in chunks])
+    dt = time.perf_counter() - t0
+    rows = [r for part in res for r in part]
+    info = {"value": n_sample / dt, "unit": "blocks/s", "cores": len(chunks), "kind": "oracle",
+            "sample": f"{n_sample} seeded blocks of the same batch (FP64 NumPy OFSE oracle, "
+                      f"{len(chunks)} processes, {dt:.1f} s)"}
+    ref = (idx,) + tuple(np.stack([r[i] for r in rows]) for i in range(4))
+    return info, ref
+
+
+def run_ofse(d_areas, d_known, target, n, args, dev, base):
+    """The same batch with the full compensation of eqs. 10-13 (OFSE)."""
+    import torch
+    from paper_2207_01205_amd import fofse as F
+    plan = F.Plan(AREA, AREA, T, K, target, device=0)
+    plan.set_compensation(F.FOFSE_COMP_FULL)
+    out = torch.empty((n, plan.nB), dtype=torch.float32, device=dev)
+    sel = torch.empty((n, K), dtype=torch.int32, device=dev)
+    coef = torch.empty((n, K, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((n,), dtype=torch.int32, device=dev)
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        F.fofse_extrapolate_batch(plan.handle, n, d_areas.data_ptr(), d_known.data_ptr(),
+                                  rg.data_ptr(), out.data_ptr(), sel.data_ptr(),
+                                  coef.data_ptr(), st.data_ptr(), stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.fofse_set_timing(plan.handle, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        step()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    kern = float(np.mean(F.fofse_kernel_times(plan.handle, args.steps))) * 1e-3
+    F.fofse_set_timing(plan.handle, False)
+    total = ev[0].elapsed_time(ev[1]) * 1e-3
+    fpb = ofse_flops_per_block(T, K)
+    res = {"value": n * args.steps / total, "unit": "blocks/s", "ms_per_step": total / args.steps * 1e3,
+           "roofline": {"bound": "alu", "kernel": "fofse_group_kernel<64, 9, true>", "flop_per_block": fpb,
+                        "avg_launch_ms": kern * 1e3, "achieved": fpb * n / kern / 1e12,
+                        "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                        "frac": fpb * n / kern / FP64_VECTOR_PEAK},
+           "block_status_nonzero": int(np.count_nonzero(st.cpu().numpy()))}
+    print(f"[bench] full compensation: {total / args.steps * 1e3:.3f} ms per step, kernel {kern * 1e3:.3f} ms",
           file=sys.stderr, flush=True)
     if base is not None:
         info, ref = base
@@ -494,6 +585,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-dct", action="store_true", help="skip the DCT-basis leg")
+    ap.add_argument("--no-ofse", action="store_true", help="skip the full-compensation (OFSE) leg")
     ap.add_argument("--mixed", type=int, default=25000, metavar="PER_CLASS",
                     help="blocks per size class of the mixed-size batch (0 = skip)")
     ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
@@ -541,6 +633,10 @@ def main():
     if not args.no_cpu_baseline and not args.no_dct:
         dct_base = dct_cpu_baseline(areas, known, target, min(DCT_SAMPLE, n),
                                     min(16, len(os.sched_getaffinity(0))))
+    ofse_base = None
+    if not args.no_cpu_baseline and not args.no_ofse:
+        ofse_base = ofse_cpu_baseline(areas, known, target, min(OFSE_SAMPLE, n),
+                                      min(16, len(os.sched_getaffinity(0))))
 
     import torch
     from paper_2207_01205_amd.fofse import Plan
@@ -687,6 +783,7 @@ def main():
         del graph
 
     dct = None if args.no_dct else run_dct(d_areas, d_known, target, n, args, dev, dct_base)
+    ofse = None if args.no_ofse else run_ofse(d_areas, d_known, target, n, args, dev, ofse_base)
     tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
     mixed = run_mixed(mixed_data, mixed_ref, args, dev) if mixed_data is not None else None
 
@@ -700,7 +797,7 @@ def main():
     fpb = flops_per_block(T, K)
     kern = float(np.mean(kern_ms)) * 1e-3
     achieved = fpb * n / kern
-    kname = "fofse_group_kernel<64,9>" if n >= 8 * 256 else "fofse_fwd_kernel<64,4>"
+    kname = "fofse_group_kernel<64, 9, false>" if n >= 8 * 256 else "fofse_fwd_kernel<64, 4>"
     result = {
         "metric": "blocks/s (16x16 loss, 48x48 area, K=200) fwd & fwd+adjoint; % FP32 VALU peak",
         "value": n * args.steps / total,
@@ -731,6 +828,7 @@ def main():
         "block_status_nonzero": int(np.count_nonzero(status)),
         "fwd_adjoint": adj,
         "dct_basis": dct,
+        "full_compensation": ofse,
     }
     if tuning is not None:
         result["tuning"] = tuning

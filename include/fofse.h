@@ -129,6 +129,30 @@ fofse_status fofse_set_path(fofse_plan plan, int32_t path);
 fofse_status fofse_set_basis(fofse_plan plan, int32_t basis);
 
 /*
+ * Orthogonality deficiency compensation (Section 2):
+ *   FOFSE_COMP_CONSTANT (default) the constant factor of eq. 14,
+ *                       c = gamma p_u (FOFSE);
+ *   FOFSE_COMP_FULL     the full compensation of eqs. 10-13 (OFSE):
+ *                       c = gamma_u p_u with gamma_u = 1 / sum_l (p_l / p_u)
+ *                       Khat_{u,l}.  With the DFT basis Khat_{u,l} = W[u-l] / W0,
+ *                       so c = R_w[u]^2 / (R_w (*) W)[u] (cyclic convolution over
+ *                       the full T x T spectrum, evaluated at the selected class
+ *                       only); c is 0 when R_w[u] or the convolution is 0, and
+ *                       real for a self-conjugate class.  gamma in d_rho_gamma
+ *                       is not used (only rho_hat is checked).  Built for
+ *                       fft_size 64 with the DFT basis; it always runs the
+ *                       grouped organisation, whatever the path setting, and
+ *                       has no adjoint.
+ * Returns FOFSE_ERR_ARG for a NULL plan or unknown mode, FOFSE_ERR_UNSUPPORTED
+ * for FOFSE_COMP_FULL with fft_size other than 64 (fofse_extrapolate_batch and
+ * fofse_backward return it for FOFSE_COMP_FULL with the DCT basis, and for the
+ * adjoint of FOFSE_COMP_FULL).
+ */
+#define FOFSE_COMP_CONSTANT 0
+#define FOFSE_COMP_FULL     1
+fofse_status fofse_set_compensation(fofse_plan plan, int32_t mode);
+
+/*
  * Extrapolate n_blocks areas of the plan's geometry (Sections 2 and 3).
  *
  * For every block b, K iterations of FOFSE run in the DFT domain: the weighted
@@ -245,8 +269,9 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  *
  * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
  * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
- * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, T exceeds 64 or the plan's basis is
- * the DCT (FOFSE_BASIS_DCT has no adjoint), FOFSE_ERR_NOMEM if
+ * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, T exceeds 64, the plan's basis is
+ * the DCT (FOFSE_BASIS_DCT has no adjoint) or its compensation is
+ * FOFSE_COMP_FULL, FOFSE_ERR_NOMEM if
  * the per-block workspace (16 B per block, used when d_grad_block is NULL) or
  * the grouped path's workspace cannot be allocated, FOFSE_ERR_DEVICE if a
  * launch fails, FOFSE_OK otherwise.

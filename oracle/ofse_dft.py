@@ -38,7 +38,9 @@ def ofse_full(f, known, T: int, rho_hat: float, K: int, weight=None):
     Returns dict with g (M, N), keys (K,), coef (K,) complex, gamma (K,)
     complex (eq. 13 factor of the selected class in every iteration; NaN when
     the residual is exactly zero and eq. 10 is 0 / 0, the iteration then adds
-    nothing)."""
+    nothing), and margin (K,) / top (K,): the selection margin
+    (|R|_(1) - |R|_(2)) / |R|_(1) over distinct classes and |R|_(1), as in the
+    FOFSE oracle."""
     f = np.asarray(f, dtype=np.float64)
     M, N = f.shape
     a = (np.asarray(known) != 0).astype(np.float64)
@@ -54,9 +56,15 @@ def ofse_full(f, known, T: int, rho_hat: float, K: int, weight=None):
     keys = np.zeros(K, np.int64)
     coef = np.zeros(K, np.complex128)
     gam = np.zeros(K, np.complex128)
+    margin = np.zeros(K)
+    top = np.zeros(K)
     for nu in range(K):
         score = np.where(canon, (R.real ** 2 + R.imag ** 2).reshape(-1), -1.0)
         best = int(np.argmax(score))                        # eq. 9, smallest key on ties
+        a1 = np.sqrt(score[best])
+        a2 = np.sqrt(max(np.delete(score, best).max(), 0.0))
+        margin[nu] = (a1 - a2) / a1 if a1 > 0.0 else 0.0
+        top[nu] = a1
         u, v = divmod(best, T)
         keys[nu] = best
         p = R / W0                                          # eq. 5 for every bin
@@ -78,4 +86,4 @@ def ofse_full(f, known, T: int, rho_hat: float, K: int, weight=None):
             G[-u % T, -v % T] += np.conj(c)
             R = R - np.conj(c) * np.roll(W, (-u, -v), axis=(0, 1))
     g = (T * T * np.fft.ifft2(G)).real[:M, :N]              # eqs. 1, 2
-    return {"g": g, "keys": keys, "coef": coef, "gamma": gam}
+    return {"g": g, "keys": keys, "coef": coef, "gamma": gam, "margin": margin, "top": top}

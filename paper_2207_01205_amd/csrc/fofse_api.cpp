@@ -19,6 +19,7 @@ struct fofse_plan_s {
     int path = FOFSE_PATH_AUTO;
     int waves = 0;                  // split path: wavefronts per block (0 = default)
     int basis = FOFSE_BASIS_DFT;
+    int comp = FOFSE_COMP_CONSTANT;
     double* d_dct_cos = nullptr;    // DCT basis: cos(pi k (2m+1) / (2T)) at [m * T + k]
     int M = 0, N = 0, T = 0, K = 0, nB = 0;
     uint8_t* d_target = nullptr;
@@ -267,6 +268,13 @@ fofse_status fofse_set_basis(fofse_plan p, int32_t basis) {
     return FOFSE_OK;
 }
 
+fofse_status fofse_set_compensation(fofse_plan p, int32_t mode) {
+    if (!p || (mode != FOFSE_COMP_CONSTANT && mode != FOFSE_COMP_FULL)) return FOFSE_ERR_ARG;
+    if (mode == FOFSE_COMP_FULL && (p->T != 64 || !grouped_supported(p))) return FOFSE_ERR_UNSUPPORTED;
+    p->comp = mode;
+    return FOFSE_OK;
+}
+
 fofse_status fofse_set_waves(fofse_plan p, int32_t waves) {
     if (!p || waves < 0) return FOFSE_ERR_ARG;
     if (!fofse::split_waves_built(p->T, waves)) return FOFSE_ERR_UNSUPPORTED;
@@ -342,6 +350,7 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         if (!d_coef) k.coef = p->d_rec_coef;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (p->basis == FOFSE_BASIS_DCT && p->comp != FOFSE_COMP_CONSTANT) return FOFSE_ERR_UNSUPPORTED;
     if (p->basis == FOFSE_BASIS_DCT) {
         fofse::Timing tm{};
         if (p->timing) {
@@ -364,10 +373,11 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         const hipError_t e = fofse::launch_dct(k, g, p->d_dct_cos, p->n_cu, st, tm);
         return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
     }
-    bool grouped = false;
+    const bool full = p->comp == FOFSE_COMP_FULL;       // built on the grouped path only
+    bool grouped = full;
     if (p->path == FOFSE_PATH_GROUPED) grouped = true;
     else if (p->path == FOFSE_PATH_AUTO)
-        grouped = grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu;
+        grouped = grouped || (grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu);
     hipError_t e;
     fofse::Timing tm{};
     if (p->timing) {
@@ -390,7 +400,7 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
             if (e != hipSuccess) return FOFSE_ERR_DEVICE;
         }
         e = p->T == 128 ? fofse::launch_grouped128(k, g, p->n_cu, st, tm)
-                        : fofse::launch_grouped(k, g, p->n_cu, st, tm);
+                        : fofse::launch_grouped(k, g, p->n_cu, st, tm, full);
     } else {
         e = fofse::launch_forward(k, st, tm);
     }
@@ -405,7 +415,8 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
     if (n_blocks == 0) return FOFSE_OK;
     if (!d_areas || !d_rho_gamma || !d_sel || !d_coef || !d_grad_out) return FOFSE_ERR_ARG;
-    if (p->K > fofse::kBackwardMaxK || p->T > 64 || p->basis != FOFSE_BASIS_DFT) return FOFSE_ERR_UNSUPPORTED;
+    if (p->K > fofse::kBackwardMaxK || p->T > 64 || p->basis != FOFSE_BASIS_DFT || p->comp != FOFSE_COMP_CONSTANT)
+        return FOFSE_ERR_UNSUPPORTED;
     DeviceGuard guard(p->device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;
     double* blk = d_grad_block;

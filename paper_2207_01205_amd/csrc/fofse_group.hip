@@ -296,7 +296,8 @@ struct GroupShared {
 
 // One work item (up to kGroup blocks of one mask class) as seen by wave WI of
 // its block.  Every wave of the workgroup runs the same sequence of barriers.
-template <int T, int WI, int MAXPX>
+// FULL selects the full compensation of eqs. 10-13 (see run_wave).
+template <int T, int WI, int MAXPX, bool FULL>
 __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& p, const GroupArgs& g,
                                              int item, int tid, int lane, int jblk, int tib,
                                              bool params_ok, double rho, double gamma) {
@@ -392,7 +393,7 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     const int bj = blk[jblk];
     const double gW0 = live ? gamma / W0 : 0.0;
     if (kWavesG > 1 || live)
-        run_wave<T, kWavesG, WI>(R, win, sh.xchg[jblk], p, bj, lane, gW0, live);
+        run_wave<T, kWavesG, WI, FULL>(R, win, sh.xchg[jblk], p, bj, lane, gW0, live);
     if (present) {
         if (!live) {          // empty record: the synthesised model is 0
             for (int it = tib; it < K; it += kWavesG * 64) {
@@ -405,7 +406,7 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     }
 }
 
-template <int T, int MAXPX>
+template <int T, int MAXPX, bool FULL = false>
 __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(KParams p, GroupArgs g) {
     constexpr int NT = kGroup * kWavesG * 64;
     static_assert(T == 64, "the window stage is written for T = 64");
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(K
     const int wi = wave % kWavesG;               // wave index within the block
     const int tib = wi * 64 + lane;              // thread index within the block
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
-    const bool params_ok = param_ok(rho) && param_ok(gamma);
+    const bool params_ok = param_ok(rho) && (FULL || param_ok(gamma));   // the full compensation has no gamma
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
 
     // items of this workgroup: a contiguous range
@@ -427,10 +428,10 @@ __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(K
 
     for (int item = i0; item < i1; ++item) {
         if constexpr (kWavesG == 1) {
-            process_item<T, 0, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+            process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
         } else {
-            if (wi == 0) process_item<T, 0, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
-            else         process_item<T, 1, MAXPX>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+            if (wi == 0) process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+            else         process_item<T, 1, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
         }
     }
 }
@@ -465,7 +466,7 @@ hipError_t launch_grouping(const GroupArgs& g, int n, hipStream_t stream) {
 }
 
 hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
-                          const Timing& tm) {
+                          const Timing& tm, bool full) {
     if (p.T != 64) return hipErrorInvalidValue;
     const hipError_t ew = launch_weights(p, stream);
     if (ew != hipSuccess) return ew;
@@ -483,8 +484,13 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
     const int mn = p.M * p.N;
     ga.n_wg = grid;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
-    if (mn <= 9 * NT) hipLaunchKernelGGL((fofse_group_kernel<64, 9>), dim3(grid), dim3(NT), 0, stream, p, ga);
-    else              hipLaunchKernelGGL((fofse_group_kernel<64, 16>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    if (full) {
+        if (mn <= 9 * NT) hipLaunchKernelGGL((fofse_group_kernel<64, 9, true>), dim3(grid), dim3(NT), 0, stream, p, ga);
+        else              hipLaunchKernelGGL((fofse_group_kernel<64, 16, true>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    } else {
+        if (mn <= 9 * NT) hipLaunchKernelGGL((fofse_group_kernel<64, 9>), dim3(grid), dim3(NT), 0, stream, p, ga);
+        else              hipLaunchKernelGGL((fofse_group_kernel<64, 16>), dim3(grid), dim3(NT), 0, stream, p, ga);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;

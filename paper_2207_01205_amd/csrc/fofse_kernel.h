@@ -109,8 +109,10 @@ int group_max_target_samples();
 hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm);
 hipError_t launch_synthesis(const KParams& p, hipStream_t stream);
 hipError_t launch_weights(const KParams& p, hipStream_t stream);
+// full: the full orthogonality deficiency compensation (eqs. 10-13) instead of
+// the constant factor of eq. 14.
 hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,
-                          const Timing& tm);
+                          const Timing& tm, bool full = false);
 hipError_t launch_clear(const GroupArgs& g, hipStream_t stream);
 hipError_t launch_fwd128(const KParams& p, hipStream_t stream);
 hipError_t launch_grouped128(const KParams& p, const GroupArgs& g, int n_cu, hipStream_t stream,

@@ -71,15 +71,73 @@ struct RegSpec {
     }
 };
 
+// Sum over every bin l of the block's full T x T spectrum of R_l W[u - l]: the
+// convolution (R (*) W)[u] of the full orthogonality deficiency compensation
+// (eqs. 10-13 with the DFT basis: sum_l p_l Khat_{u,l} = (p (*) W)[u] / W0).
+// For a wavefront that holds a whole block (rows 0..T/2, lane = column): a
+// stored row k in 1..T/2-1 stands for itself and for its conjugate row T - k
+// (R_{-l} = conj(R_l), W[u + l] read as in the update), rows 0 and T/2 are
+// stored whole and count once.  The window reads are those of the update.
+template <int T, int WI>
+__device__ __forceinline__ double2 conv_at(const RegSpec<WaveRows<T, 1, WI>::S>& R, const double2* win,
+                                           int u, int v, int lane) {
+    using L = Layout<T, 1>;
+    using WR = WaveRows<T, 1, WI>;
+    constexpr int S = WR::S;
+    constexpr int H = L::H;
+    constexpr int Q = L::Q;
+    const int l = lane;
+    const int cA = (l - v) & (T - 1), cB = (v - l) & (T - 1);
+    const int cC = (l + v) & (T - 1), cD = (-l - v) & (T - 1);
+    const double2* b1d = win + (WR::r1d - u + Q) * T + cA;
+    const double2* b1m = win + (u - WR::r1m + Q) * T + cB;
+    const double2* b2d = win + (WR::r2d + u + Q) * T + cC;
+    const double2* b2m = win + (T - WR::r2m - u + Q) * T + cD;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = WR::k0 + s;
+        const double2 x1 = (k >= Q) ? b1d[(k - WR::r1d) * T] : b1m[(WR::r1m - k) * T];
+        const double2 x2 = (k <= Q) ? b2d[(k - WR::r2d) * T] : b2m[(WR::r2m - k) * T];
+        // W1 = W[k - u], W2 = W[k + u] (a mirrored read is the conjugate)
+        const double w1r = x1.x, w1i = k < Q ? -x1.y : x1.y;
+        const double w2r = x2.x, w2i = k > Q ? -x2.y : x2.y;
+        const double rr = R.gr(s), ri = R.gi(s);
+        sr = fma(rr, w1r, sr);            // R conj(W1)
+        sr = fma(ri, w1i, sr);
+        si = fma(ri, w1r, si);
+        si = fma(-rr, w1i, si);
+        if (k != 0 && k != H) {           // conj(R) W2 for the conjugate row
+            sr = fma(rr, w2r, sr);
+            sr = fma(ri, w2i, sr);
+            si = fma(rr, w2i, si);
+            si = fma(-ri, w2r, si);
+        }
+    }
+    if (!(lane < T)) sr = si = 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+    }
+    return make_double2(readlane_f64(sr, 0), readlane_f64(si, 0));
+}
+
 // One wave's share of the K iterations of one block.  The selection record
 // (class key and coefficient of every iteration) goes to p.sel / p.coef; the
 // model on B is synthesised from it by the synthesis kernel.  ``live`` = false runs the
 // same barriers without writing (a wave of a missing or flagged block in a
 // workgroup whose waves synchronise every iteration).
-template <int T, int NW, int WI>
+//
+// FULL = false: the constant compensation of eq. 14, c = gamma R[u] / W0
+// (gW0 = gamma / W0).  FULL = true (one wavefront per block): the full
+// compensation of eqs. 10-13, c = gamma_u p_u = R[u]^2 / (R (*) W)[u], 0 when
+// either factor is 0; gW0 is unused.
+template <int T, int NW, int WI, bool FULL = false>
 __device__ __forceinline__ void run_wave(RegSpec<WaveRows<T, NW, WI>::S>& R,
         const double2* win, Xchg<NW>* xchg, const KParams& p, int b, int lane, double gW0,
         bool live = true) {
+    static_assert(!FULL || NW == 1, "the full compensation is built for one wavefront per block");
     using L = Layout<T, NW>;
     using WR = WaveRows<T, NW, WI>;
     constexpr int S = WR::S;
@@ -225,8 +283,19 @@ __device__ __forceinline__ void run_wave(RegSpec<WaveRows<T, NW, WI>::S>& R,
         u = u > H ? H : u;
         // eqs. 5 and 14: c = gamma R[u] / W0; a self-conjugate class keeps Re c
         const bool selfc = (u == 0 || u == H) && (v == 0 || v == H);
-        const double cre = wv.x * gW0;
-        const double cim = selfc ? 0.0 : wv.y * gW0;
+        double cre, cim;
+        if constexpr (FULL) {
+            // eqs. 10-13: c = R[u]^2 / (R (*) W)[u]
+            const double2 cv = conv_at<T, WI>(R, win, u, v, lane);
+            const double den = cv.x * cv.x + cv.y * cv.y;
+            const double nr = wv.x * wv.x - wv.y * wv.y, ni = 2.0 * wv.x * wv.y;
+            const bool ok = den > 0.0 && (wv.x != 0.0 || wv.y != 0.0);
+            cre = ok ? (nr * cv.x + ni * cv.y) / den : 0.0;
+            cim = ok && !selfc ? (ni * cv.x - nr * cv.y) / den : 0.0;
+        } else {
+            cre = wv.x * gW0;
+            cim = selfc ? 0.0 : wv.y * gW0;
+        }
         if (live && WI == 0 && lane == 0) {
             const size_t r = (size_t)b * K + it;
             p.sel[r] = v * T + u;

@@ -34,8 +34,11 @@ FOFSE_PATH_GROUPED = 2
 FOFSE_BASIS_DFT = 0
 FOFSE_BASIS_DCT = 1
 
+FOFSE_COMP_CONSTANT = 0
+FOFSE_COMP_FULL = 1
+
 EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves",
-            "fofse_set_basis",
+            "fofse_set_basis", "fofse_set_compensation",
             "fofse_extrapolate_batch",
             "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
             "fofse_status_str")
@@ -78,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_set_waves.restype = ctypes.c_int
     L.fofse_set_basis.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_basis.restype = ctypes.c_int
+    L.fofse_set_compensation.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_compensation.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
     L.fofse_backward.argtypes = [vp, ctypes.c_int32] + [vp] * 10
@@ -136,6 +141,12 @@ def fofse_set_basis(plan: int, basis: int) -> None:
     st = load_library().fofse_set_basis(plan, int(basis))
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_set_basis")
+
+
+def fofse_set_compensation(plan: int, mode: int) -> None:
+    st = load_library().fofse_set_compensation(plan, int(mode))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_compensation")
 
 
 def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int,
@@ -204,6 +215,10 @@ class Plan:
         """FOFSE_BASIS_DFT (default) or FOFSE_BASIS_DCT; with the DCT the
         record holds keys k*T + l in [0, T*T) and real coefficients (c, 0)."""
         fofse_set_basis(self.handle, basis)
+
+    def set_compensation(self, mode: int):
+        """FOFSE_COMP_CONSTANT (eq. 14, default) or FOFSE_COMP_FULL (eqs. 10-13)."""
+        fofse_set_compensation(self.handle, mode)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -54,6 +54,7 @@ def test_null_arguments_rejected_without_gpu():
     assert L.fofse_set_path(None, 0) == F.FOFSE_ERR_ARG
     assert L.fofse_set_waves(None, 2) == F.FOFSE_ERR_ARG
     assert L.fofse_set_basis(None, F.FOFSE_BASIS_DCT) == F.FOFSE_ERR_ARG
+    assert L.fofse_set_compensation(None, F.FOFSE_COMP_FULL) == F.FOFSE_ERR_ARG
     assert L.fofse_backward(None, 1, *([None] * 10)) == F.FOFSE_ERR_ARG
     assert L.fofse_backward(None, 0, *([None] * 10)) == F.FOFSE_ERR_ARG
     assert L.fofse_set_timing(None, 1) == F.FOFSE_ERR_ARG
