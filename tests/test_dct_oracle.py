@@ -167,3 +167,14 @@ def test_product_to_sum_identity():
     # the extension is exact: Wc at 2T - a equals -Wc at a, and Wc at T is 0
     np.testing.assert_allclose(Wc[T], 0.0, atol=1e-12 * np.abs(Wc).max())
     np.testing.assert_allclose(Wc[2 * T - 5], -Wc[5], atol=1e-12 * np.abs(Wc).max())
+
+
+def test_batch_equals_single_calls():
+    T, M, N = 16, 12, 11
+    f1, k1 = _area(M, N, 21, ((3, 7), (2, 6)))
+    f2, k2 = _area(M, N, 22, ((5, 9), (4, 8)))
+    both = fofse_dct(np.stack([f1, f2]), np.stack([k1, k2]), T, 0.8, 0.5, 15)
+    for i, (f, k) in enumerate(((f1, k1), (f2, k2))):
+        one = fofse_dct(f, k, T, 0.8, 0.5, 15)
+        assert np.array_equal(both.keys[i], one.keys)
+        np.testing.assert_allclose(both.g[i], one.g, rtol=0, atol=1e-12 * np.abs(one.g).max())

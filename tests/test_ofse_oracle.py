@@ -37,3 +37,20 @@ def test_orthogonal_weighting_gives_unit_compensation():
     ref = fofse(f, known, T, 1.0, 1.0, K)
     np.testing.assert_array_equal(got["keys"], ref.keys)
     np.testing.assert_allclose(got["g"], ref.g, atol=1e-9)
+
+
+def test_selection_margin_matches_fofse_before_the_first_update():
+    """Both oracles select on the same spectrum in the first iteration, so the
+    reported margin and largest magnitude agree there (and so does the key)."""
+    from oracle.fofse_dft import fofse
+    rng = np.random.default_rng(17)
+    M, N, T = 12, 10, 16
+    f = 100 + 30 * rng.normal(size=(M, N))
+    known = np.ones((M, N), np.uint8)
+    known[4:8, 3:7] = 0
+    a = ofse_full(f, known, T, 0.8, 3)
+    b = fofse(f, known, T, 0.8, 0.5, 3)
+    assert a["keys"][0] == b.keys[0]
+    np.testing.assert_allclose(a["margin"][0], b.margin[0], rtol=1e-12)
+    np.testing.assert_allclose(a["top"][0], b.top[0], rtol=1e-12)
+    assert np.all(a["margin"] >= 0) and np.all(a["top"] > 0)
