@@ -26,23 +26,41 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+         # no packed FP32 instructions anywhere in the device code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # IEEE mode off: v_max_f64 needs no operand canonicalisation (the
+         # kernels carry no NaNs; input checks test exponent bits instead)
+         "-mno-amdgpu-ieee", "-fno-honor-nans",
+         "-Wno-unused-command-line-argument"]
+
+def _check(res, cmd):
+    if res.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed")
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source for gfx950 and link libfofse.so; returns its path."""
+    """Compile every source for gfx950 (one object each, compiled side by side)
+    and link libfofse.so; returns its path."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj] + list(extra)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    for cmd, proc in jobs:
+        out, err = proc.communicate()
+        _check(subprocess.CompletedProcess(cmd, proc.returncode, out, err), cmd)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # no packed FP32 instructions anywhere in the device code
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           # IEEE mode off: v_max_f64 needs no operand canonicalisation (the
-           # kernels carry no NaNs; input checks test exponent bits instead)
-           "-mno-amdgpu-ieee", "-fno-honor-nans",
-           "-Wno-unused-command-line-argument",
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + list(extra)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
+    _check(subprocess.run(cmd, capture_output=True, text=True), cmd)
     os.replace(tmp, LIB)
     return LIB
 

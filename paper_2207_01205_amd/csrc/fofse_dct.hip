@@ -20,11 +20,15 @@
 //
 // Organisation.  One wavefront per block: lane = column index l, register slot
 // = row index k (64 doubles per lane).  Blocks with one support mask share w
-// and so the table; a workgroup takes up to four of them (the work items of
-// the device-side grouping) and builds the table once.  Per iteration a lane
-// reads four table entries per slot: two columns (|l - v| and the fold of
-// l + v, fixed for the lane) in two rows (|k - u| and the fold of k + u,
-// uniform for the slot).  The iteration loop has no barrier.
+// and so the table; a workgroup of eight wavefronts takes up to eight of them
+// (one or two work items of the device-side grouping) and builds the table
+// once.  Per iteration a lane needs four table entries per slot: two columns
+// (|l - v| and the fold of l + v, fixed for the lane) in two rows (k - u and
+// k + u, uniform for the slot).  The table is stored row-extended (rows -64 ..
+// 127, the row fold and its sign applied), so that both rows advance with the
+// slot: every read is at a compile-time offset from four per-iteration
+// addresses, and a row's 64 columns are consecutive doubles (8-byte reads
+// without bank conflicts).  The iteration loop has no barrier.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -37,26 +41,35 @@ namespace fofse {
 namespace {
 
 constexpr int kT = kDctT;
-constexpr int kTP = kT + 1;                 // table row stride; index T holds 0
-constexpr int kNT = 64 * kGroup;            // one wavefront per block
+constexpr int kWv = 8;                      // wavefronts (blocks) per workgroup
+constexpr int kNT = 64 * kWv;
+constexpr int kRW = kT / kWv;               // rows per wavefront in the transforms
+constexpr int kTP = kT + 1;                 // row stride of the column pass
 constexpr int kBufLen = kT * kTP;           // >= T * T
+constexpr int kRows = 192;                  // rows of the extended table (-64 .. 127)
 constexpr double kA0 = 0.125;               // sqrt(1/64)
 constexpr double kA1 = 0.1767766952966369;  // sqrt(2/64)
-constexpr int kAhead = 3;                   // slots whose table reads are in flight
+constexpr int kAhead = 6;                   // slots whose table reads are in flight
+static_assert(2 * kGroup == kWv, "a workgroup takes two work items of the grouping");
 
 typedef double d16 __attribute__((ext_vector_type(16)));
 
+// E[a][b] = Wc[a][b] for 0 <= a < T, Wc[-a][b] for -T < a < 0, -Wc[2T - a][b]
+// for T < a < 2T, 0 for a = +-T; columns b < T (column T is 0).  E[a][b] is
+// ext[(a + 64) * T + b].
 struct DctShared {
-    double tab[kTP * kTP];   // Wc; while the blocks are transformed: one block's R at [k * T + l]
-    double buf[kBufLen];     // column pass at [n * kTP + k]; during the iterations C(u, m) at [m * T + u]
-    int flags[kGroup];
+    double ext[kRows * kT];     // while the blocks are transformed: column pass + one block's R
+    double cs[kT * kT];         // C(u, m) at [m * T + u], for the synthesis
+    int flags[kWv];
 };
+
+__device__ __forceinline__ int ext_index(int a, int b) { return (a + 64) * kT + b; }
 
 __device__ __forceinline__ bool known_sample(const uint8_t* known, const uint8_t* target, size_t base, int i) {
     return target[i] == 0 && (known == nullptr || known[base + i] != 0);
 }
 
-// P[n][k] = sum_m C(k, m) X[m][n] for n < N and the 16 rows k of wave wv, with
+// P[n][k] = sum_m C(k, m) X[m][n] for n < N and the kRW rows k of wave wv, with
 // X = w on the support of the item's mask, times f of block b when b >= 0.
 // Written to buf[n * kTP + k].  A non-finite known sample of block b sets
 // FOFSE_BLOCK_NONFINITE in *flag (its contribution is 0).
@@ -64,9 +77,9 @@ __device__ __forceinline__ void column_pass(double* buf, const KParams& p, const
                                             int b, int* flag, const double* __restrict__ cosm, int wv, int lane) {
     const int M = p.M, N = p.N, MN = M * N;
     const bool col = lane < N;
-    double acc[16];
+    double acc[kRW];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kRW; ++j) acc[j] = 0.0;
     for (int m = 0; m < M; ++m) {
         double x = 0.0;
         if (col) {
@@ -82,26 +95,26 @@ __device__ __forceinline__ void column_pass(double* buf, const KParams& p, const
                 }
             }
         }
-        const double* cr = cosm + m * kT + 16 * wv;       // C(16 wv + j, m), uniform
+        const double* cr = cosm + m * kT + kRW * wv;      // C(kRW wv + j, m), uniform
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = fma(cr[j], x, acc[j]);
+        for (int j = 0; j < kRW; ++j) acc[j] = fma(cr[j], x, acc[j]);
     }
     if (col) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) buf[lane * kTP + 16 * wv + j] = acc[j];
+        for (int j = 0; j < kRW; ++j) buf[lane * kTP + kRW * wv + j] = acc[j];
     }
 }
 
-// acc[j] = sum_{n < N} P[n][16 wv + j] C(l, n) for the lane's column l.
-__device__ __forceinline__ void row_pass(double (&acc)[16], const double* buf, int N,
+// acc[j] = sum_{n < N} P[n][kRW wv + j] C(l, n) for the lane's column l.
+__device__ __forceinline__ void row_pass(double (&acc)[kRW], const double* buf, int N,
                                          const double* __restrict__ cosm, int wv, int lane) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kRW; ++j) acc[j] = 0.0;
     for (int n = 0; n < N; ++n) {
         const double c = cosm[n * kT + lane];
-        const double* pr = buf + n * kTP + 16 * wv;        // uniform: broadcast reads
+        const double* pr = buf + n * kTP + kRW * wv;       // uniform: broadcast reads
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = fma(pr[j], c, acc[j]);
+        for (int j = 0; j < kRW; ++j) acc[j] = fma(pr[j], c, acc[j]);
     }
 }
 
@@ -134,9 +147,36 @@ __device__ __forceinline__ double fetch_slot(const d16 (&R)[4], int k, int lane)
     }
 }
 
+// R[k][l] -= q_k <Gram sum> for the 64 rows of column l = lane, and the
+// largest key.  t[0..3] point at the entries of slot 0 (rows -u and u in the
+// columns |l - v| and fold(l + v)); slot k reads 64 k doubles further on.
+__device__ __forceinline__ double update_rows(d16 (&R)[4], const double* const (&t)[4], double sgnB,
+                                              double q0, double q1) {
+    constexpr int NB = kAhead + 1;
+    double x[NB][4];
+    auto load = [&](int k, double* y) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[q] = t[q][k * kT];
+    };
+#pragma unroll
+    for (int k = 0; k < kAhead; ++k) load(k, x[k]);
+    double best = 0.0;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+        if (k + kAhead < 64) load(k + kAhead, x[(k + kAhead) % NB]);
+        const double* y = x[k % NB];
+        const double s = fma(sgnB, y[1], y[0]) + fma(sgnB, y[3], y[2]);
+        const double r = fma(k == 0 ? -q0 : -q1, s, R[k >> 4][k & 15]);
+        R[k >> 4][k & 15] = r;
+        best = max_abs(best, key_of(r, k));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return best;
+}
+
 // The K iterations of one block held by this wavefront (R: slot k of chunk
 // k / 16 at element k % 16).  Writes the selection record of block b.
-__device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* tab, const KParams& p, int b, int lane,
+__device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* e, const KParams& p, int b, int lane,
                                             double gamma) {
     constexpr int T = kT;
     const int K = p.K;
@@ -144,39 +184,14 @@ __device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* tab, cons
     int u = 0, v = 0;
     double q0 = 0.0, q1 = 0.0;          // update scale of row 0 and of rows 1..T-1 in this column
     for (int it = 0;; ++it) {
-        // R[k][l] -= c <w phi_u, phi_{k,l}> for the 64 rows of column l = lane,
-        // then the key of each row.  Pass 0 runs with c = 0 (R unchanged).
+        // Pass 0 runs with c = 0 (R unchanged).
         const int cA = lane >= v ? lane - v : v - lane;
         const int sb = lane + v;
-        const int cB = sb <= T ? sb : 2 * T - sb;
-        const double sB = sb <= T ? 1.0 : -1.0;
-        const double* pA = tab + cA;
-        const double* pB = tab + cB;
-        // the reads of slot k + kAhead are issued before slot k is computed
-        double t[kAhead][4];
-        auto load = [&](int k, double* x) {
-            const int rA = k >= u ? k - u : u - k;
-            const int rs = k + u;
-            const int rB = rs <= T ? rs : 2 * T - rs;
-            x[0] = pA[rA * kTP];
-            x[1] = pB[rA * kTP];
-            x[2] = pA[rB * kTP];
-            x[3] = pB[rB * kTP];
-        };
-#pragma unroll
-        for (int k = 0; k < kAhead; ++k) load(k, t[k]);
-        double best = 0.0;
-#pragma unroll
-        for (int k = 0; k < 64; ++k) {
-            const double sR = k + u <= T ? 1.0 : -1.0;
-            double* x = t[k % kAhead];
-            const double s = fma(sR, fma(sB, x[3], x[2]), fma(sB, x[1], x[0]));
-            if (k + kAhead < 64) load(k + kAhead, x);
-            const double r = fma(k == 0 ? -q0 : -q1, s, R[k >> 4][k & 15]);
-            R[k >> 4][k & 15] = r;
-            best = max_abs(best, key_of(r, k));
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        const int cB = sb < T ? sb : (sb == T ? 0 : 2 * T - sb);
+        const double sgnB = sb < T ? 1.0 : (sb == T ? 0.0 : -1.0);
+        const double* t[4] = {e + ext_index(-u, cA), e + ext_index(-u, cB), e + ext_index(u, cA),
+                              e + ext_index(u, cB)};
+        const double best = update_rows(R, t, sgnB, q0, q1);
         if (it == K) break;
 
         // eq. 9 over the wavefront: the largest high word, then among those the
@@ -190,11 +205,15 @@ __device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* tab, cons
         const double Ru = fetch_slot<0, 64>(R, uk, vl);
 
         // eq. 5: <phi_u, phi_u>_w is the Gram entry at k = u (rows 0 and 2u,
-        // columns 0 and 2v); eq. 14: c = gamma p
+        // columns 0 and 2v of Wc); eq. 14: c = gamma p
         const int d1 = 2 * uk, d2 = 2 * vl;
         const int f1 = d1 <= T ? d1 : 2 * T - d1, f2 = d2 <= T ? d2 : 2 * T - d2;
         const double s1 = d1 <= T ? 1.0 : -1.0, s2 = d2 <= T ? 1.0 : -1.0;
-        const double wsum = tab[0] + s2 * tab[f2] + s1 * (tab[f1 * kTP] + s2 * tab[f1 * kTP + f2]);
+        const double w00 = e[ext_index(0, 0)];
+        const double w02 = f2 < T ? e[ext_index(0, f2)] : 0.0;
+        const double w10 = e[ext_index(f1, 0)];                 // row T of E is 0
+        const double w12 = f2 < T ? e[ext_index(f1, f2)] : 0.0;
+        const double wsum = w00 + s2 * w02 + s1 * (w10 + s2 * w12);
         const double au1 = uk == 0 ? kA0 : kA1, au2 = vl == 0 ? kA0 : kA1;
         const double S = 0.25 * (au1 * au1) * (au2 * au2) * wsum;
         const double c = S > 0.0 ? gamma * Ru / S : 0.0;
@@ -249,24 +268,17 @@ __device__ __forceinline__ void dct_synthesis(const double* cs, const KParams& p
     }
 }
 
-// One work item: up to kGroup blocks of one support mask.
+// Up to kWv blocks of one support mask, blk[0 .. nblk).
 __device__ __forceinline__ void dct_item(DctShared& sh, const KParams& p, const GroupArgs& g,
-                                         const double* __restrict__ cosm, int item, int tid, int lane,
-                                         int wv, bool params_ok, double gamma) {
-    const int M = p.M, N = p.N, MN = M * N, K = p.K;
-    int nblk, blk[kGroup];
-    if (g.direct) {
-        nblk = min(kGroup, p.n_blocks - item * kGroup);
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) blk[j] = item * kGroup + j;
-    } else {
-        nblk = g.item_n[item];
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) blk[j] = g.item_blk[(size_t)item * kGroup + j];
-    }
+                                         const double* __restrict__ cosm, const int (&blk)[kWv], int nblk,
+                                         int tid, int lane, int wv, bool params_ok, double gamma) {
+    const int MN = p.M * p.N, N = p.N, K = p.K;
     const size_t rep_base = (size_t)blk[0] * MN;    // every block of the item has this mask
+    double* buf = sh.ext;
+    double* stage = buf + kBufLen;
+    double* e = buf;
     __syncthreads();                                 // the previous item is done with the LDS
-    if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    if (tid < kWv) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
 
     d16 R[4];
@@ -275,48 +287,55 @@ __device__ __forceinline__ void dct_item(DctShared& sh, const KParams& p, const 
     if (params_ok) {
         // R = DCT(w f) of each block (eqs. 7, 8), staged in the table's space
         const double al = lane == 0 ? kA0 : kA1;
-        for (int j = 0; j < kGroup; ++j) {
+        for (int j = 0; j < kWv; ++j) {
             if (j >= nblk) break;                    // uniform over the workgroup
-            column_pass(sh.buf, p, g, rep_base, blk[j], &sh.flags[j], cosm, wv, lane);
+            column_pass(buf, p, g, rep_base, blk[j], &sh.flags[j], cosm, wv, lane);
             __syncthreads();
-            double acc[16];
-            row_pass(acc, sh.buf, N, cosm, wv, lane);
+            double acc[kRW];
+            row_pass(acc, buf, N, cosm, wv, lane);
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const int k = 16 * wv + jj;
-                sh.tab[k * kT + lane] = acc[jj] * al * (k == 0 ? kA0 : kA1);
+            for (int jj = 0; jj < kRW; ++jj) {
+                const int k = kRW * wv + jj;
+                stage[k * kT + lane] = acc[jj] * al * (k == 0 ? kA0 : kA1);
             }
             __syncthreads();
             if (wv == j) {
 #pragma unroll
-                for (int k = 0; k < 64; ++k) R[k >> 4][k & 15] = sh.tab[k * kT + lane];
+                for (int k = 0; k < 64; ++k) R[k >> 4][k & 15] = stage[k * kT + lane];
             }
         }
-        // the table Wc of the item's w; the last block's reads of the staging
-        // finish before the barrier that precedes the table writes
-        column_pass(sh.buf, p, g, rep_base, -1, nullptr, cosm, wv, lane);
+        // the table Wc of the item's w, written row-extended once every read
+        // of the column pass and of the staging is done
+        column_pass(buf, p, g, rep_base, -1, nullptr, cosm, wv, lane);
         __syncthreads();
-        double acc[16];
-        row_pass(acc, sh.buf, N, cosm, wv, lane);
+        double acc[kRW];
+        row_pass(acc, buf, N, cosm, wv, lane);
+        __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) sh.tab[(16 * wv + jj) * kTP + lane] = acc[jj];
-        if (tid < kTP) sh.tab[kT * kTP + tid] = 0.0;
-        if (tid < kT) sh.tab[tid * kTP + kT] = 0.0;
-        __syncthreads();
-        // cosine table for the synthesis, over the column pass's space
-        for (int i = tid; i < kT * kT; i += kNT) sh.buf[i] = cosm[i];
+        for (int jj = 0; jj < kRW; ++jj) {
+            const int k = kRW * wv + jj;
+            e[ext_index(k, lane)] = acc[jj];
+            e[ext_index(-k, lane)] = acc[jj];
+            if (k > 0) e[ext_index(2 * kT - k, lane)] = -acc[jj];
+        }
+        if (tid < kT) {
+            e[ext_index(kT, tid)] = 0.0;
+            e[ext_index(-kT, tid)] = 0.0;
+        }
         __syncthreads();
     }
 
     const bool present = wv < nblk;
     int flags = present ? sh.flags[wv] : 0;
-    const double W0 = params_ok ? sh.tab[0] : 0.0;   // Wc[0][0] = sum of the weights
+    const double W0 = params_ok ? e[ext_index(0, 0)] : 0.0;   // Wc[0][0] = sum of the weights
     if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
     const bool live = present && flags == 0;
-    const int bj = blk[wv < kGroup ? wv : 0];
+    int bj = blk[0];                                 // blk[wv] without a run-time register index
+#pragma unroll
+    for (int j = 1; j < kWv; ++j) bj = wv == j ? blk[j] : bj;
     if (live) {
-        dct_iterate(R, sh.tab, p, bj, lane, gamma);
-        dct_synthesis(sh.buf, p, bj, lane);
+        dct_iterate(R, sh.ext, p, bj, lane, gamma);
+        dct_synthesis(sh.cs, p, bj, lane);
     } else if (present) {                            // empty record, model 0
         for (int it = lane; it < K; it += 64) {
             const size_t r = (size_t)bj * K + it;
@@ -329,19 +348,45 @@ __device__ __forceinline__ void dct_item(DctShared& sh, const KParams& p, const 
     if (present && lane == 0 && p.status) p.status[bj] = flags;
 }
 
-__global__ __launch_bounds__(kNT, 2) void fofse_dct_kernel(KParams p, GroupArgs g,
+// Each workgroup takes a contiguous range of the grouping's work items (up to
+// kGroup blocks of one mask each) and runs them one at a time, or two at a
+// time when the next item of the range has the same mask (then the first one
+// is full: only the last item of a class can be partial).  Without a known
+// array every block has the one mask and the items are kWv consecutive blocks.
+__global__ __launch_bounds__(kNT, 1) void fofse_dct_kernel(KParams p, GroupArgs g,
                                                             const double* __restrict__ cosm) {
     __shared__ DctShared sh;
     const int tid = (int)__builtin_amdgcn_workitem_id_x(), lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && param_ok(gamma);
-    // items of this workgroup: a contiguous range
-    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
+    for (int i = tid; i < kT * kT; i += kNT) sh.cs[i] = cosm[i];   // visible after the first item's barrier
+    const int n_items = g.direct ? (p.n_blocks + kWv - 1) / kWv : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
     const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
     const int i1 = min(n_items, i0 + per);
-    for (int item = i0; item < i1; ++item) dct_item(sh, p, g, cosm, item, tid, lane, wv, params_ok, gamma);
+    for (int item = i0; item < i1;) {
+        int nblk, blk[kWv];
+        if (g.direct) {
+            nblk = min(kWv, p.n_blocks - item * kWv);
+#pragma unroll
+            for (int j = 0; j < kWv; ++j) blk[j] = item * kWv + (j < nblk ? j : 0);
+            item += 1;
+        } else {
+            const int n0 = g.item_n[item];
+            const int cls = g.item_cls[item];
+            const bool two = item + 1 < i1 && n0 == kGroup && cls >= 0 && g.item_cls[item + 1] == cls;
+            const int n1 = two ? g.item_n[item + 1] : 0;
+            nblk = n0 + n1;
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                blk[j] = g.item_blk[(size_t)item * kGroup + (j < n0 ? j : 0)];
+                blk[kGroup + j] = two && j < n1 ? g.item_blk[(size_t)(item + 1) * kGroup + j] : blk[0];
+            }
+            item += two ? 2 : 1;
+        }
+        dct_item(sh, p, g, cosm, blk, nblk, tid, lane, wv, params_ok, gamma);
+    }
 }
 
 }  // namespace
@@ -358,8 +403,9 @@ hipError_t launch_dct(const KParams& p, const GroupArgs& g, const double* cosm, 
         const hipError_t eg = launch_grouping(ga, p.n_blocks, stream);
         if (eg != hipSuccess) return eg;
     }
-    const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
-    int grid = 2 * n_cu;
+    // one workgroup per compute unit (the LDS holds one)
+    const int max_items = g.direct ? (p.n_blocks + kWv - 1) / kWv : p.n_blocks;
+    int grid = n_cu;
     if (grid > max_items) grid = max_items;
     ga.n_wg = grid;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
