@@ -47,6 +47,7 @@ constexpr int kRW = kT / kWv;               // rows per wavefront in the transfo
 constexpr int kTP = kT + 1;                 // row stride of the column pass
 constexpr int kBufLen = kT * kTP;           // >= T * T
 constexpr int kRows = 192;                  // rows of the extended table (-64 .. 127)
+constexpr int kCS = kT + 1;                 // row stride of the synthesis cosine table
 constexpr double kA0 = 0.125;               // sqrt(1/64)
 constexpr double kA1 = 0.1767766952966369;  // sqrt(2/64)
 constexpr int kAhead = 6;                   // slots whose table reads are in flight
@@ -59,7 +60,7 @@ typedef double d16 __attribute__((ext_vector_type(16)));
 // ext[(a + 64) * T + b].
 struct DctShared {
     double ext[kRows * kT];     // while the blocks are transformed: column pass + one block's R
-    double cs[kT * kT];         // C(u, m) at [m * T + u], for the synthesis
+    double cs[kT * kCS];        // C(u, m) at [u * kCS + m], for the synthesis
     int flags[kWv];
 };
 
@@ -233,7 +234,7 @@ __device__ __forceinline__ void dct_iterate(d16 (&R)[4], const double* e, const 
 
 // g on B = sum_nu c_nu phi_{u_nu} from the record this wavefront wrote (read
 // back with cache-bypassing loads after the release fence); cs holds C(u, m)
-// at [m * T + u].
+// at [u * kCS + m], so that lanes of different pixels read different banks.
 __device__ __forceinline__ void dct_synthesis(const double* cs, const KParams& p, int b, int lane) {
     const int K = p.K, N = p.N, nB = p.nB;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -244,8 +245,6 @@ __device__ __forceinline__ void dct_synthesis(const double* cs, const KParams& p
         const bool ok = q < nB;
         const int i = ok ? p.bpix[q] : 0;
         const int m = i / N, n = i - m * N;
-        const double* cm = cs + m * kT;
-        const double* cn = cs + n * kT;
         double acc = 0.0;
         for (int nu0 = 0; nu0 < K; nu0 += 64) {
             const int nu = nu0 + lane;
@@ -261,7 +260,7 @@ __device__ __forceinline__ void dct_synthesis(const double* cs, const KParams& p
                 const double cj = readlane_f64(c, j);
                 const int u1 = (kj >> 6) & 63, u2 = kj & 63;
                 const double s = cj * (u1 == 0 ? kA0 : kA1) * (u2 == 0 ? kA0 : kA1);
-                acc = fma(s, cm[u1] * cn[u2], acc);
+                acc = fma(s, cs[u1 * kCS + m] * cs[u2 * kCS + n], acc);
             }
         }
         if (ok) p.out[(size_t)b * nB + q] = (float)acc;
@@ -360,7 +359,8 @@ __global__ __launch_bounds__(kNT, 1) void fofse_dct_kernel(KParams p, GroupArgs 
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && param_ok(gamma);
-    for (int i = tid; i < kT * kT; i += kNT) sh.cs[i] = cosm[i];   // visible after the first item's barrier
+    for (int i = tid; i < kT * kT; i += kNT)                        // visible after the first item's barrier
+        sh.cs[(i & (kT - 1)) * kCS + (i >> 6)] = cosm[i];
     const int n_items = g.direct ? (p.n_blocks + kWv - 1) / kWv : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
     const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
