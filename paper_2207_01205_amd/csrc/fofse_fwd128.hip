@@ -16,8 +16,8 @@
 //   * W stays in LDS as its row half.  A read W[r][c] with r outside 0..64 is
 //     conj(W[-r][-c]) (w is real); for every register slot the choice between
 //     the direct and the mirrored read is uniform (it depends on the slot's row
-//     and the selected u only), and the conjugation is folded into the signs of
-//     the coefficient.
+//     and the selected u only); the conjugation flips the sign bit of the read's
+//     imaginary part.
 //   * After the transforms each wavefront puts its rows in natural column order,
 //     so that neighbouring lanes read neighbouring entries of W.
 

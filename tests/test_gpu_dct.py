@@ -183,3 +183,39 @@ def test_dct_unsupported_configurations():
     with pytest.raises(FofseError) as e:
         plan.backward(a, rg, sel, coef, go)
     assert e.value.status == FOFSE_ERR_UNSUPPORTED
+
+
+def test_dct_items_of_every_class_size():
+    """Classes of 1 to 12 blocks in a shuffled batch: the kernel runs the
+    grouping's items of four one or two at a time (two when the next item of a
+    workgroup's range has the same mask), so class sizes 5..8 and 9..12 pair a
+    full item with a partial one.  Every block equals its result when run alone,
+    and a sample matches the oracle."""
+    rng = np.random.default_rng(11)
+    M = N = 48
+    target = np.zeros((M, N), np.uint8)
+    target[16:32, 16:32] = 1
+    sizes = [1, 3, 4, 5, 8, 9, 2, 1, 12, 7, 6, 11, 10]
+    masks, areas = [], []
+    m = np.arange(M)[:, None]
+    nn = np.arange(N)[None, :]
+    for c, sz in enumerate(sizes):
+        kn = (1 - target).copy()
+        kn[rng.random((M, N)) < 0.15] = 0            # holes of this class
+        for _ in range(sz):
+            masks.append(kn)
+            areas.append(100 + 40 * np.cos(2 * np.pi * (rng.uniform(0.02, 0.2) * m + rng.uniform(0.02, 0.2) * nn))
+                         + 8 * rng.normal(size=(M, N)))
+    order = rng.permutation(len(masks))
+    known = np.stack(masks)[order].astype(np.uint8)
+    areas = np.stack(areas)[order].astype(np.float32)
+    plan = _plan(M, N, 60, target)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, f"{len(sizes)} classes, {len(order)} blocks")
+    assert np.all(st == 0)
+    for b in range(len(order)):
+        o1, s1, c1, t1 = run_gpu(plan, areas[b:b + 1], known[b:b + 1], 0.8, 0.5, f"block {b} alone")
+        assert np.array_equal(out[b], o1[0]) and np.array_equal(sel[b], s1[0]) and np.array_equal(coef[b], c1[0])
+    pick = np.arange(0, len(order), 5)
+    ref = oracle_on(areas[pick], known[pick], target, 64, 0.8, 0.5, 60)
+    same = check_parity(ref, target, out[pick], sel[pick], coef[pick], st[pick], "class sizes 1..12, sampled")
+    assert same.sum() >= len(pick) - 1
