@@ -139,12 +139,14 @@ fofse_status fofse_set_basis(fofse_plan plan, int32_t basis);
  *                       the full T x T spectrum, evaluated at the selected class
  *                       only); c is 0 when R_w[u] or the convolution is 0, and
  *                       real for a self-conjugate class.  gamma in d_rho_gamma
- *                       is not used (only rho_hat is checked).  Built for
- *                       fft_size 64 with the DFT basis; it always runs the
- *                       grouped organisation, whatever the path setting, and
- *                       has no adjoint.
+ *                       is not used (only rho_hat is checked).  Built with
+ *                       the DFT basis for fft_size 64 (always the grouped
+ *                       organisation, whatever the path setting) and for
+ *                       fft_size 16 and 32 (one wavefront per block, whatever
+ *                       the fofse_set_waves setting); no adjoint.
  * Returns FOFSE_ERR_ARG for a NULL plan or unknown mode, FOFSE_ERR_UNSUPPORTED
- * for FOFSE_COMP_FULL with fft_size other than 64 (fofse_extrapolate_batch and
+ * for FOFSE_COMP_FULL with fft_size 128, or 64 with an area or B beyond the
+ * grouped organisation's limits (fofse_extrapolate_batch and
  * fofse_backward return it for FOFSE_COMP_FULL with the DCT basis, and for the
  * adjoint of FOFSE_COMP_FULL).
  */

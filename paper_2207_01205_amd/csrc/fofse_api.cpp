@@ -270,7 +270,8 @@ fofse_status fofse_set_basis(fofse_plan p, int32_t basis) {
 
 fofse_status fofse_set_compensation(fofse_plan p, int32_t mode) {
     if (!p || (mode != FOFSE_COMP_CONSTANT && mode != FOFSE_COMP_FULL)) return FOFSE_ERR_ARG;
-    if (mode == FOFSE_COMP_FULL && (p->T != 64 || !grouped_supported(p))) return FOFSE_ERR_UNSUPPORTED;
+    if (mode == FOFSE_COMP_FULL && !(p->T == 16 || p->T == 32 || (p->T == 64 && grouped_supported(p))))
+        return FOFSE_ERR_UNSUPPORTED;
     p->comp = mode;
     return FOFSE_OK;
 }
@@ -373,8 +374,10 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         const hipError_t e = fofse::launch_dct(k, g, p->d_dct_cos, p->n_cu, st, tm);
         return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
     }
-    const bool full = p->comp == FOFSE_COMP_FULL;       // built on the grouped path only
-    bool grouped = full;
+    // the full compensation: grouped organisation at T = 64, one wavefront per
+    // block at T = 16 and 32
+    const bool full = p->comp == FOFSE_COMP_FULL;
+    bool grouped = full && p->T == 64;
     if (p->path == FOFSE_PATH_GROUPED) grouped = true;
     else if (p->path == FOFSE_PATH_AUTO)
         grouped = grouped || (grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu);
@@ -402,7 +405,7 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
         e = p->T == 128 ? fofse::launch_grouped128(k, g, p->n_cu, st, tm)
                         : fofse::launch_grouped(k, g, p->n_cu, st, tm, full);
     } else {
-        e = fofse::launch_forward(k, st, tm);
+        e = fofse::launch_forward(k, st, tm, full);
     }
     return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
 }

@@ -44,7 +44,7 @@ namespace fofse {
 // R of this wave's rows from the transform Z = W + jR sitting in LDS in the
 // FFT's output order, then the residual iteration.  Contains the two barriers
 // that turn the LDS grid into the W window (all waves reach them).
-template <int T, int NW, int WI, int WPT>
+template <int T, int NW, int WI, int WPT, bool FULL>
 __device__ __forceinline__ void wave_body(double2* win, Xchg<NW>* xchg, const KParams& p, int b,
                                           int tid, int lane, const double2* wv, double gW0,
                                           int flags_pre, int* s_flags) {
@@ -75,10 +75,12 @@ __device__ __forceinline__ void wave_body(double2* win, Xchg<NW>* xchg, const KP
     __syncthreads();
     const int flags = *s_flags | flags_pre;
     if (flags == 0)
-        run_wave<T, NW, WI>(R, win, xchg, p, b, lane, gW0);
+        run_wave<T, NW, WI, FULL>(R, win, xchg, p, b, lane, gW0);
 }
 
-template <int T, int NW>
+// FULL: the full compensation of eqs. 10-13 instead of eq. 14 (one wavefront
+// per block; gamma is not used).
+template <int T, int NW, bool FULL = false>
 __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
     using L = Layout<T, NW>;
     constexpr int NT = L::NT;
@@ -100,7 +102,8 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
 
     for (int i = tid; i < T; i += NT) tw[i] = p.twiddle[i];
     for (int i = tid; i < T * T; i += NT) win[i] = make_double2(0.0, 0.0);
-    if (tid == 0) s_flags = param_ok(rho) && param_ok(gamma) ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    const bool params_ok = param_ok(rho) && (FULL || param_ok(gamma));
+    if (tid == 0) s_flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     __syncthreads();
 
     // eqs. 4, 15: w = rho_hat^dist on A;  z = w + j w f, placed transposed
@@ -139,7 +142,6 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
         return win[FftPlan<T>::perm(kr & (T - 1)) * T + FftPlan<T>::perm(kc & (T - 1))];
     };
     const double W0 = win[0].x;
-    const bool params_ok = param_ok(rho) && param_ok(gamma);
     const int flags_pre = (!params_ok || W0 > 0.0) ? 0 : FOFSE_BLOCK_NO_SUPPORT;
     const double gW0 = gamma / W0;
     double2 wv[WPT];
@@ -155,10 +157,10 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
         }
     }
 
-    if (wave == 0) wave_body<T, NW, 0, WPT>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 1) if (wave == 1) wave_body<T, NW, 1, WPT>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 2) if (wave == 2) wave_body<T, NW, 2, WPT>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 3) if (wave == 3) wave_body<T, NW, 3, WPT>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
+    if (wave == 0) wave_body<T, NW, 0, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
+    if constexpr (NW > 1) if (wave == 1) wave_body<T, NW, 1, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
+    if constexpr (NW > 2) if (wave == 2) wave_body<T, NW, 2, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
+    if constexpr (NW > 3) if (wave == 3) wave_body<T, NW, 3, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
 
     const int flags = s_flags | flags_pre;
     if (flags != 0) {          // empty record: the synthesised model is 0
@@ -175,9 +177,9 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int T, int NW>
+template <int T, int NW, bool FULL = false>
 static hipError_t launch_fwd(const KParams& p, hipStream_t stream) {
-    hipLaunchKernelGGL((fofse_fwd_kernel<T, NW>), dim3(p.n_blocks), dim3(NW * 64), 0, stream, p);
+    hipLaunchKernelGGL((fofse_fwd_kernel<T, NW, FULL>), dim3(p.n_blocks), dim3(NW * 64), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -215,13 +217,15 @@ hipError_t launch_weights(const KParams& p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm) {
+hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm, bool full) {
     if (p.T != 128 && p.T != 64 && p.T != 32 && p.T != 16) return hipErrorInvalidValue;
+    if (full && p.T != 32 && p.T != 16) return hipErrorInvalidValue;
     hipError_t e = launch_weights(p, stream);
     if (e != hipSuccess) return e;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
     const int nw = p.waves;
-    if (p.T == 128) e = launch_fwd128(p, stream);
+    if (full) e = p.T == 32 ? launch_fwd<32, 1, true>(p, stream) : launch_fwd<16, 1, true>(p, stream);
+    else if (p.T == 128) e = launch_fwd128(p, stream);
     else if (p.T == 64) e = nw == 2 ? launch_fwd<64, 2>(p, stream) : nw == 8 ? launch_fwd<64, 8>(p, stream)
                                     : launch_fwd<64, kWaves64>(p, stream);
     else if (p.T == 32) e = nw == 1 ? launch_fwd<32, 1>(p, stream) : nw == 4 ? launch_fwd<32, 4>(p, stream)

@@ -106,7 +106,9 @@ struct Timing {
 int max_target_samples(int T);
 int group_max_target_samples();
 
-hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm);
+// Per-block organisation (T = 16, 32, 64, 128).  full: the full compensation
+// (eqs. 10-13), built for T = 16 and 32 with one wavefront per block.
+hipError_t launch_forward(const KParams& p, hipStream_t stream, const Timing& tm, bool full = false);
 hipError_t launch_synthesis(const KParams& p, hipStream_t stream);
 hipError_t launch_weights(const KParams& p, hipStream_t stream);
 // full: the full orthogonality deficiency compensation (eqs. 10-13) instead of

@@ -20,15 +20,15 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _plan(M, N, K, target):
+def _plan(M, N, K, target, T=64):
     from paper_2207_01205_amd.fofse import FOFSE_COMP_FULL, Plan
-    plan = Plan(M, N, 64, K, target, device=0)
+    plan = Plan(M, N, T, K, target, device=0)
     plan.set_compensation(FOFSE_COMP_FULL)
     return plan
 
 
 def run_gpu(plan, areas, known, rho, gamma, label):
-    print(f"[gpu] OFSE {label}: n={areas.shape[0]} M={plan.M} N={plan.N} K={plan.K}", flush=True)
+    print(f"[gpu] OFSE {label}: n={areas.shape[0]} M={plan.M} N={plan.N} T={plan.T} K={plan.K}", flush=True)
     dev = torch.device("cuda", 0)
     a = torch.from_numpy(np.ascontiguousarray(areas, dtype=np.float32)).to(dev)
     k = None if known is None else torch.from_numpy(np.ascontiguousarray(known, dtype=np.uint8)).to(dev)
@@ -38,11 +38,11 @@ def run_gpu(plan, areas, known, rho, gamma, label):
     return out.cpu().numpy(), sel.cpu().numpy(), coef.cpu().numpy(), st.cpu().numpy()
 
 
-def oracle_on(areas, known, target, rho, K):
+def oracle_on(areas, known, target, rho, K, T=64):
     f = np.asarray(areas, dtype=np.float32).astype(np.float64)
     kn = (np.broadcast_to(1 - target, f.shape) if known is None else known).astype(np.uint8)
     kn = kn * (1 - target)[None]
-    res = [ofse_full(np.where(kn[b] != 0, f[b], 0.0), kn[b], 64, rho, K) for b in range(f.shape[0])]
+    res = [ofse_full(np.where(kn[b] != 0, f[b], 0.0), kn[b], T, rho, K) for b in range(f.shape[0])]
     return {key: np.stack([r[key] for r in res]) for key in ("g", "keys", "coef", "margin", "top")}
 
 
@@ -117,10 +117,10 @@ def test_ofse_edge_cases_and_unsupported():
     check_parity(ref, A.target, out[ok], sel[ok], coef[ok], st[ok], "edge cases (regular blocks)")
     _, _, _, st2 = run_gpu(plan, areas, known, 1.5, 0.5, "rho 1.5")
     assert np.all(st2 == FOFSE_BLOCK_BAD_PARAM)
-    # not built: T other than 64, the adjoint, the DCT basis
-    p32 = Plan(16, 16, 32, 10, np.pad(np.ones((4, 4), np.uint8), 6), device=0)
+    # not built: T = 128, the adjoint, the DCT basis
+    p128 = Plan(64, 64, 128, 10, np.pad(np.ones((32, 32), np.uint8), 16), device=0)
     with pytest.raises(FofseError) as e:
-        p32.set_compensation(FOFSE_COMP_FULL)
+        p128.set_compensation(FOFSE_COMP_FULL)
     assert e.value.status == FOFSE_ERR_UNSUPPORTED
     dev = torch.device("cuda", 0)
     a = torch.from_numpy(areas).to(dev)
@@ -135,3 +135,30 @@ def test_ofse_edge_cases_and_unsupported():
     with pytest.raises(FofseError) as e:
         plan.extrapolate(a, rg)
     assert e.value.status == FOFSE_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("T,block,support,K", [(16, 4, 4, 32), (32, 8, 8, 64)])
+def test_ofse_small_fft_sizes(T, block, support, K):
+    """T = 16 and 32 (one wavefront per block): the 4x4 and 8x8 losses of the
+    mixed-size workload, with canonical masks and with per-block holes in the
+    support, against the FP64 OFSE oracle at the same T."""
+    rng = np.random.default_rng(T)
+    side = block + 2 * support
+    target = np.zeros((side, side), np.uint8)
+    target[support:support + block, support:support + block] = 1
+    n = 40
+    m = np.arange(side)[:, None]
+    nn = np.arange(side)[None, :]
+    areas = np.stack([100 + 45 * np.cos(2 * np.pi * (rng.uniform(0.02, 0.3) * m + rng.uniform(0.02, 0.3) * nn))
+                      + 6 * rng.normal(size=(side, side)) for _ in range(n)]).astype(np.float32)
+    plan = _plan(side, side, K, target, T=T)
+    out, sel, coef, st = run_gpu(plan, areas, None, 0.8, 0.5, f"T={T} canonical")
+    ref = oracle_on(areas, None, target, 0.8, K, T=T)
+    same = check_parity(ref, target, out, sel, coef, st, f"T={T} canonical")
+    assert same.sum() >= n - 2
+    known = np.broadcast_to(1 - target, areas.shape).copy()
+    known[rng.random(known.shape) < 0.1] = 0
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, f"T={T} per-block holes")
+    ref = oracle_on(areas, known, target, 0.8, K, T=T)
+    same = check_parity(ref, target, out, sel, coef, st, f"T={T} per-block holes")
+    assert same.sum() >= n - 2
