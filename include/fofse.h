@@ -117,11 +117,12 @@ fofse_status fofse_set_path(fofse_plan plan, int32_t path);
  *                   every R_w[k] (eq. 3).  fofse_extrapolate_batch then writes
  *                   keys k*T + l in [0, T*T) to d_sel and (c, 0) to d_coef;
  *                   blocks with identical support masks share a workgroup,
- *                   whatever the path setting.  fft_size 64 only; no adjoint.
+ *                   whatever the path setting.  fft_size 16, 32 or 64; no
+ *                   adjoint.
  * Results of one basis never depend on the other's settings.  Selecting the
  * DCT uploads a T x T cosine table on first use (synchronous).
  * Returns FOFSE_ERR_ARG for a NULL plan or unknown basis,
- * FOFSE_ERR_UNSUPPORTED for the DCT with fft_size other than 64,
+ * FOFSE_ERR_UNSUPPORTED for the DCT with fft_size 128,
  * FOFSE_ERR_NOMEM / FOFSE_ERR_DEVICE if the table cannot be uploaded.
  */
 #define FOFSE_BASIS_DFT 0

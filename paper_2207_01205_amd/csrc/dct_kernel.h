@@ -8,11 +8,11 @@
 
 namespace fofse {
 
-// FFT size of the DCT-basis path (the grid is kDctT x kDctT).
-constexpr int kDctT = 64;
+// Grid sizes T of the DCT-basis path (the grid is T x T): 16, 32 and 64.
+bool dct_size_supported(int T);
 
 // Forward iterations with the orthonormal DCT-II basis for n blocks.  Blocks
-// of one support mask share a workgroup (kGroup of them, one wavefront each);
+// of one support mask share a workgroup (up to 2 kGroup of them, one wavefront each);
 // g holds the grouping workspace when p.known is not null.  cosm is the
 // device table cos(pi k (2m+1) / (2T)) at [m * T + k], m, k < T.  The model on
 // B is written to p.out and the selection record to p.sel / p.coef.

@@ -246,7 +246,7 @@ fofse_status fofse_set_path(fofse_plan p, int32_t path) {
 fofse_status fofse_set_basis(fofse_plan p, int32_t basis) {
     if (!p || (basis != FOFSE_BASIS_DFT && basis != FOFSE_BASIS_DCT)) return FOFSE_ERR_ARG;
     if (basis == FOFSE_BASIS_DCT) {
-        if (p->T != fofse::kDctT) return FOFSE_ERR_UNSUPPORTED;
+        if (!fofse::dct_size_supported(p->T)) return FOFSE_ERR_UNSUPPORTED;
         if (!p->d_dct_cos) {
             const int T = p->T;
             std::vector<double> c((size_t)T * T);

@@ -169,9 +169,11 @@ def test_dct_unsupported_configurations():
     from paper_2207_01205_amd.fofse import FOFSE_BASIS_DCT, FOFSE_ERR_UNSUPPORTED, FofseError, Plan
     target = np.zeros((16, 16), np.uint8)
     target[6:10, 6:10] = 1
-    p32 = Plan(16, 16, 32, 10, target, device=0)
+    big = np.zeros((64, 64), np.uint8)
+    big[16:48, 16:48] = 1
+    p128 = Plan(64, 64, 128, 10, big, device=0)
     with pytest.raises(FofseError) as e:
-        p32.set_basis(FOFSE_BASIS_DCT)
+        p128.set_basis(FOFSE_BASIS_DCT)
     assert e.value.status == FOFSE_ERR_UNSUPPORTED
     plan = _plan(16, 16, 10, target)
     dev = torch.device("cuda", 0)
@@ -219,3 +221,41 @@ def test_dct_items_of_every_class_size():
     ref = oracle_on(areas[pick], known[pick], target, 64, 0.8, 0.5, 60)
     same = check_parity(ref, target, out[pick], sel[pick], coef[pick], st[pick], "class sizes 1..12, sampled")
     assert same.sum() >= len(pick) - 1
+
+
+@pytest.mark.parametrize("T,block,support,K", [(16, 4, 4, 32), (32, 8, 8, 64)])
+def test_dct_small_grid_sizes(T, block, support, K):
+    """T = 16 and 32 (lanes T..63 of each wavefront idle): the 4x4 and 8x8
+    losses of the mixed-size workload, canonical masks (items of eight
+    consecutive blocks, a ragged last one) and per-block masks in classes of
+    several sizes, against the FP64 DCT oracle at the same T."""
+    rng = np.random.default_rng(100 + T)
+    side = block + 2 * support
+    target = np.zeros((side, side), np.uint8)
+    target[support:support + block, support:support + block] = 1
+    m = np.arange(side)[:, None]
+    nn = np.arange(side)[None, :]
+    n = 45
+    areas = np.stack([100 + 45 * np.cos(2 * np.pi * (rng.uniform(0.02, 0.3) * m + rng.uniform(0.02, 0.3) * nn))
+                      + 6 * rng.normal(size=(side, side)) for _ in range(n)]).astype(np.float32)
+    plan = _plan(side, side, K, target, T=T)
+    out, sel, coef, st = run_gpu(plan, areas, None, 0.85, 0.5, f"T={T} canonical")
+    assert np.all((sel >= 0) & (sel < T * T))
+    ref = oracle_on(areas, None, target, T, 0.85, 0.5, K)
+    same = check_parity(ref, target, out, sel, coef, st, f"T={T} canonical")
+    assert same.sum() >= n - 2
+    # per-block masks: 9 classes of 1..9 blocks in a shuffled order
+    masks = []
+    for c in range(9):
+        kn = (1 - target).copy()
+        kn[rng.random(kn.shape) < 0.12] = 0
+        masks += [kn] * (c + 1)
+    order = rng.permutation(len(masks))[:n]
+    known = np.stack(masks)[order].astype(np.uint8)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.85, 0.5, f"T={T} per-block masks")
+    ref = oracle_on(areas, known, target, T, 0.85, 0.5, K)
+    same = check_parity(ref, target, out, sel, coef, st, f"T={T} per-block masks")
+    assert same.sum() >= n - 2
+    for b in (0, 7, n - 1):
+        o1, s1, c1, _ = run_gpu(plan, areas[b:b + 1], known[b:b + 1], 0.85, 0.5, f"T={T} block {b} alone")
+        assert np.array_equal(out[b], o1[0]) and np.array_equal(sel[b], s1[0]) and np.array_equal(coef[b], c1[0])
