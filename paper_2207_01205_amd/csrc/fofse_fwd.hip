@@ -162,7 +162,8 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
     if constexpr (NW > 2) if (wave == 2) wave_body<T, NW, 2, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
     if constexpr (NW > 3) if (wave == 3) wave_body<T, NW, 3, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
 
-    const int flags = s_flags | flags_pre;
+    // parameters out of range: that flag alone (as on every other path)
+    const int flags = params_ok ? (s_flags | flags_pre) : FOFSE_BLOCK_BAD_PARAM;
     if (flags != 0) {          // empty record: the synthesised model is 0
         for (int it = tid; it < K; it += NT) {
             p.sel[(size_t)b * K + it] = 0;

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(NW * 64, 1) void fofse_fwd128_kernel(KParams p) {
     auto wval = [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; };
     wave128_dispatch<NW, 0>(wave, sh, p, b, tid, lane, gamma, flags_pre, wval);
     // flags are final after the W transform (all waves passed its barriers)
-    int flags = sh.flags;
+    int flags = params_ok ? sh.flags : FOFSE_BLOCK_BAD_PARAM;   // out-of-range parameters: that flag alone
     const double W0 = sh.spec[0].x;
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
     if (flags != 0) {          // empty record: the synthesised model is 0
@@ -423,7 +423,7 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
     row_half_spectrum<NT>(sh.spec, sh.tw, M, N, tid,
                           [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; });
     const double W0 = sh.spec[0].x;
-    int flags = sh.flags[jb];
+    int flags = params_ok ? sh.flags[jb] : FOFSE_BLOCK_BAD_PARAM;   // out-of-range parameters: that flag alone
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
     const bool live = present && flags == 0;
     run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg[jb], p, bj, lane, live ? gamma / W0 : 0.0, live);

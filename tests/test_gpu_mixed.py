@@ -186,3 +186,39 @@ def test_mixed_batch_graph_and_autotune(frame_img):
     ref = fofse(f, kn, T, 0.8, 0.5, K)
     ok, _ = selection_parity(sel.cpu().numpy()[:12], ref.keys, ref.margin, 1e-6, top_ref=ref.top)
     assert ok.all()
+
+
+@pytest.mark.parametrize("T,side,path,waves,comp", [
+    (16, 12, "split", 1, "constant"), (32, 24, "split", 2, "constant"), (64, 48, "split", 4, "constant"),
+    (64, 48, "grouped", 0, "constant"), (128, 64, "split", 8, "constant"), (128, 64, "grouped", 0, "constant"),
+    (32, 24, "split", 0, "full"), (64, 48, "grouped", 0, "full")])
+def test_bad_parameters_flag_alone_on_every_path(T, side, path, waves, comp):
+    """rho_hat outside (0, 1]: every block reports FOFSE_BLOCK_BAD_PARAM and
+    nothing else, also a block with a non-finite known sample or no support,
+    and its record and model are zero, on every organisation."""
+    from paper_2207_01205_amd.fofse import (FOFSE_BLOCK_BAD_PARAM, FOFSE_COMP_FULL, FOFSE_PATH_GROUPED,
+                                            FOFSE_PATH_SPLIT, Plan)
+    rng = np.random.default_rng(T)
+    target = np.zeros((side, side), np.uint8)
+    q = side // 4
+    target[q:side - q, q:side - q] = 1
+    areas = (100 + 20 * rng.normal(size=(6, side, side))).astype(np.float32)
+    known = np.broadcast_to(1 - target, areas.shape).copy()
+    areas[2, 0, 0] = np.nan
+    known[4] = 0
+    plan = Plan(side, side, T, 20, target, device=0)
+    plan.set_path(FOFSE_PATH_GROUPED if path == "grouped" else FOFSE_PATH_SPLIT)
+    if waves:
+        plan.set_waves(waves)
+    if comp == "full":
+        plan.set_compensation(FOFSE_COMP_FULL)
+    dev = torch.device("cuda", 0)
+    print(f"[gpu] bad parameters: T={T} {path} waves={waves} {comp}", flush=True)
+    a = torch.from_numpy(areas).to(dev)
+    k = torch.from_numpy(known).to(dev)
+    rg = torch.tensor([1.5, 0.5], dtype=torch.float64, device=dev)
+    out, sel, coef, st = plan.extrapolate(a, rg, known=k, record=True)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert np.all(st == FOFSE_BLOCK_BAD_PARAM), st
+    assert np.all(out.cpu().numpy() == 0) and np.all(sel.cpu().numpy() == 0) and np.all(coef.cpu().numpy() == 0)

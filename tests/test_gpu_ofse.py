@@ -162,3 +162,32 @@ def test_ofse_small_fft_sizes(T, block, support, K):
     ref = oracle_on(areas, known, target, 0.8, K, T=T)
     same = check_parity(ref, target, out, sel, coef, st, f"T={T} per-block holes")
     assert same.sum() >= n - 2
+
+
+def test_ofse_small_fft_edge_cases():
+    """T = 32 with the full compensation: a non-finite known sample, a block
+    with no support, gamma outside (0, 1] (ignored), rho outside it (flagged),
+    K = 0, and the wave setting ignored (one wavefront per block)."""
+    from paper_2207_01205_amd.fofse import FOFSE_BLOCK_BAD_PARAM, FOFSE_BLOCK_NONFINITE, FOFSE_BLOCK_NO_SUPPORT
+    rng = np.random.default_rng(3)
+    side, T, K = 24, 32, 40
+    target = np.zeros((side, side), np.uint8)
+    target[8:16, 8:16] = 1
+    areas = (120 + 30 * rng.normal(size=(7, side, side))).astype(np.float32)
+    known = np.broadcast_to(1 - target, areas.shape).copy()
+    areas[1, 0, 0] = np.inf
+    known[4] = 0
+    plan = _plan(side, side, K, target, T=T)
+    plan.set_waves(4)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 3.0, "T=32 edge cases")
+    assert st[1] == FOFSE_BLOCK_NONFINITE and st[4] == FOFSE_BLOCK_NO_SUPPORT
+    for b in (1, 4):
+        assert np.all(out[b] == 0) and np.all(sel[b] == 0) and np.all(coef[b] == 0)
+    ok = [0, 2, 3, 5, 6]
+    ref = oracle_on(areas[ok], known[ok], target, 0.8, K, T=T)
+    check_parity(ref, target, out[ok], sel[ok], coef[ok], st[ok], "T=32 edge cases (regular blocks)")
+    _, _, _, st2 = run_gpu(plan, areas, known, 1.5, 0.5, "T=32 rho 1.5")
+    assert np.all(st2 == FOFSE_BLOCK_BAD_PARAM)
+    plan0 = _plan(side, side, 0, target, T=T)
+    out3, _, _, st3 = run_gpu(plan0, areas[:3], known[:3], 0.8, 0.5, "T=32 K = 0")
+    assert np.all(st3[[0, 2]] == 0) and np.all(out3 == 0)
