@@ -24,7 +24,11 @@
 //      lane scan, a wavefront reduction and one LDS exchange between the waves
 //      of the workgroup; c = gamma R[u]/W0 (eqs. 5, 14); every stored bin gets
 //      R[k] -= c W[k-u] + conj(c) W[k+u] (eq. 3 via the DFT shift theorem);
-//      the model is accumulated directly on the missing area (eqs. 1, 2).
+//      the selection record (class key and c of every iteration) is written,
+//      and the synthesis kernel builds the model on the missing area from it
+//      (eqs. 1, 2).
+//   A compile-time variant (FULL, one wavefront per block, T = 16 and 32)
+//   takes c from the full compensation of eqs. 10-13 instead of eq. 14.
 //
 // No MFMA: the update is a shifted rank-2 update, not a contraction.
 
