@@ -173,6 +173,27 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// A double moved across lanes by a DPP control, both 32-bit halves (0 in the
+// rows the row mask leaves out).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of a double over the 64 lanes by the exchanges of wave_max_u32 (quads,
+// half rows, rows, then the row broadcasts into lane 63); the result is uniform.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1, 0xF>(v);           // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);           // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);          // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);          // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);          // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);          // row_bcast:31 into rows 2 and 3
+    return readlane_f64(v, 63);
+}
+
 // max of two doubles as one v_max_f64 (the operands are finite keys; no
 // operand canonicalisation or absolute value is wanted)
 __device__ __forceinline__ double max_f64(double a, double b) {

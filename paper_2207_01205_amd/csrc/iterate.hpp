@@ -115,12 +115,7 @@ __device__ __forceinline__ double2 conv_at(const RegSpec<WaveRows<T, 1, WI>::S>&
         }
     }
     if (!(lane < T)) sr = si = 0.0;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sr += __shfl_xor(sr, off, 64);
-        si += __shfl_xor(si, off, 64);
-    }
-    return make_double2(readlane_f64(sr, 0), readlane_f64(si, 0));
+    return make_double2(wave_sum_f64(sr), wave_sum_f64(si));
 }
 
 // One wave's share of the K iterations of one block.  The selection record
