@@ -373,6 +373,88 @@ def sample_parity(ref, gpu_out, gpu_sel):
             "max_abs_dg": float(err[same].max()) if same.any() else None, "failures": fails}
 
 
+SMALL_SAMPLE = 4       # oracle-checked blocks per class and variant of the small-size leg
+
+
+def _small_oracle(args):
+    areas, target, T_, K_, variant = args
+    kn = np.broadcast_to(1 - target, areas.shape).astype(np.uint8)
+    f = areas.astype(np.float32).astype(np.float64)
+    sel_b = target.reshape(-1) == 1
+    if variant == "dct":
+        from oracle.fofse_dct import fofse_dct
+        r = fofse_dct(np.where(kn != 0, f, 0.0), kn, T_, RHO, GAMMA, K_)
+        return r.g.reshape(len(f), -1)[:, sel_b], r.keys, r.margin, r.top
+    from oracle.ofse_dft import ofse_full
+    res = [ofse_full(np.where(kn[b] != 0, f[b], 0.0), kn[b], T_, RHO, K_) for b in range(len(f))]
+    return (np.stack([x["g"].reshape(-1)[sel_b] for x in res]), np.stack([x["keys"] for x in res]),
+            np.stack([x["margin"] for x in res]), np.stack([x["top"] for x in res]))
+
+
+def run_small_variants(classes, args, dev):
+    """The DCT basis and the full compensation at T = 16 and 32, on the 4x4 and
+    8x8 classes of the mixed-size batch (canonical masks): blocks/s, the
+    kernel's HIP-event mean, its rate on the algorithmic FLOPs, and parity of
+    a few oracle-checked blocks."""
+    import torch
+    from paper_2207_01205_amd import fofse as F
+    out_all = {}
+    for c in classes:
+        if c["T"] not in (16, 32):
+            continue
+        T_, K_, A = c["T"], c["K"], c["areas"].shape[1]
+        n = len(c["areas"])
+        d_areas = torch.from_numpy(c["areas"]).to(dev)
+        for variant in ("dct", "full"):
+            plan = F.Plan(A, A, T_, K_, c["target"], device=0)
+            if variant == "dct":
+                plan.set_basis(F.FOFSE_BASIS_DCT)
+                fpb, kname = dct_flops_per_block(T_, K_), f"fofse_dct_kernel<{T_}>"
+            else:
+                plan.set_compensation(F.FOFSE_COMP_FULL)
+                fpb, kname = ofse_flops_per_block(T_, K_), f"fofse_fwd_kernel<{T_}, 1, true>"
+            out = torch.empty((n, plan.nB), dtype=torch.float32, device=dev)
+            sel = torch.empty((n, K_), dtype=torch.int32, device=dev)
+            coef = torch.empty((n, K_, 2), dtype=torch.float64, device=dev)
+            st = torch.empty((n,), dtype=torch.int32, device=dev)
+            rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+            stream = torch.cuda.current_stream(dev)
+
+            def step():
+                F.fofse_extrapolate_batch(plan.handle, n, d_areas.data_ptr(), 0, rg.data_ptr(), out.data_ptr(),
+                                          sel.data_ptr(), coef.data_ptr(), st.data_ptr(), stream.cuda_stream)
+
+            for _ in range(max(1, args.warmup)):
+                step()
+            torch.cuda.synchronize()
+            F.fofse_set_timing(plan.handle, True)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(args.steps):
+                step()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            kern = float(np.mean(F.fofse_kernel_times(plan.handle, args.steps))) * 1e-3
+            total = ev[0].elapsed_time(ev[1]) * 1e-3
+            res = {"blocks": n, "value": n * args.steps / total, "unit": "blocks/s",
+                   "ms_per_step": total / args.steps * 1e3,
+                   "roofline": {"bound": "alu", "kernel": kname, "flop_per_block": fpb,
+                                "avg_launch_ms": kern * 1e3, "achieved": fpb * n / kern / 1e12,
+                                "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                                "frac": fpb * n / kern / FP64_VECTOR_PEAK},
+                   "block_status_nonzero": int(np.count_nonzero(st.cpu().numpy()))}
+            if not args.no_cpu_baseline:
+                idx = np.arange(SMALL_SAMPLE)
+                g, keys, margin, top = _small_oracle((c["areas"][:SMALL_SAMPLE], c["target"], T_, K_, variant))
+                res["sample_parity"] = sample_parity((idx, g, keys, margin, top), out.cpu().numpy(),
+                                                     sel.cpu().numpy())
+            print(f"[bench] {variant} T={T_}: {res['ms_per_step']:.3f} ms per step, kernel {kern * 1e3:.3f} ms",
+                  file=sys.stderr, flush=True)
+            out_all[f"{variant}_T{T_}"] = res
+            plan.close()
+    return out_all
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -586,6 +668,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-dct", action="store_true", help="skip the DCT-basis leg")
     ap.add_argument("--no-ofse", action="store_true", help="skip the full-compensation (OFSE) leg")
+    ap.add_argument("--small-variants", action="store_true",
+                    help="also time the DCT basis and the full compensation at T = 16 and 32 on the mixed batch's "
+                         "4x4 and 8x8 classes (needs --mixed > 0)")
     ap.add_argument("--mixed", type=int, default=25000, metavar="PER_CLASS",
                     help="blocks per size class of the mixed-size batch (0 = skip)")
     ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
@@ -786,6 +871,8 @@ def main():
     ofse = None if args.no_ofse else run_ofse(d_areas, d_known, target, n, args, dev, ofse_base)
     tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
     mixed = run_mixed(mixed_data, mixed_ref, args, dev) if mixed_data is not None else None
+    small = (run_small_variants(mixed_data, args, dev)
+             if args.small_variants and mixed_data is not None else None)
 
     # final full-batch pass for the outputs checked below
     step()
@@ -834,6 +921,8 @@ def main():
         result["tuning"] = tuning
     if mixed is not None:
         result["mixed"] = mixed
+    if small is not None:
+        result["small_variants"] = small
     if base is not None:
         info, ref = base
         info["sample_parity"] = sample_parity(ref, out_h, sel_h)
