@@ -691,7 +691,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
-              "(blocks are independent; see the sharding notes in the design document).",
+              "(blocks are independent: a multi-GPU run would shard the block list; it is not built).",
               file=sys.stderr)
         sys.exit(2)
 
