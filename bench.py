@@ -164,7 +164,7 @@ def _oracle_chunk(args):
     f = areas.astype(np.float32).astype(np.float64)
     kn = known * (1 - target)[None]
     r = fofse(f, kn, T, RHO, GAMMA, K)
-    return r.g.reshape(len(f), -1)[:, target.reshape(-1) == 1], r.keys, r.margin, r.top
+    return r.g.reshape(len(f), -1)[:, target.reshape(-1) == 1], r.keys, r.margin, r.top, r.coef, r.W0
 
 
 def cpu_baseline(areas, known, target, n_sample: int, workers: int):
@@ -176,17 +176,14 @@ def cpu_baseline(areas, known, target, n_sample: int, workers: int):
     with mp.get_context("fork").Pool(workers) as pool:
         res = pool.map(_oracle_chunk, [(areas[c], known[c], target) for c in chunks])
     dt = time.perf_counter() - t0
-    g = np.concatenate([r[0] for r in res])
-    keys = np.concatenate([r[1] for r in res])
-    margin = np.concatenate([r[2] for r in res])
-    top = np.concatenate([r[3] for r in res])
+    g, keys, margin, top, coef, W0 = (np.concatenate([r[i] for r in res]) for i in range(6))
     info = {
         "value": n_sample / dt, "unit": "blocks/s", "cores": workers, "kind": "oracle",
         "sample": f"{n_sample} seeded blocks of the same batch (FP64 NumPy DFT-domain oracle, "
                   f"{workers} processes, {dt:.1f} s)",
         "cpu_model": _cpu_model(),
     }
-    return info, (idx, g, keys, margin, top)
+    return info, (idx, g, keys, margin, top, coef, W0)
 
 
 DCT_SAMPLE = 64        # oracle-checked blocks of the DCT-basis leg
@@ -355,22 +352,28 @@ def run_ofse(d_areas, d_known, target, n, args, dev, base):
     return res
 
 
-def sample_parity(ref, gpu_out, gpu_sel):
-    """Compare the GPU's outputs with the oracle sample (parity rule)."""
-    from oracle.fofse_dft import selection_parity
-    idx, g, keys, margin, top = ref
+def sample_parity(ref, gpu_out, gpu_sel, gpu_coef=None):
+    """Compare the GPU's outputs with the oracle sample (parity rule).  With the
+    GPU record's coefficients and the oracle's (constant compensation, DFT
+    basis) also the largest difference of the selected |R_w[u]| relative to
+    A0, against the rule's rounding floor."""
+    from oracle.fofse_dft import FLOOR, divergence_report, selection_parity, spectral_drift
+    idx, g, keys, margin, top = ref[:5]
     ok, div = selection_parity(gpu_sel[idx], keys, margin, top_ref=top)
     same = np.all(gpu_sel[idx] == keys, axis=1)
     err = np.abs(gpu_out[idx] - g).max(axis=1)
-    fails = []
-    for j in np.nonzero(~ok)[0][:5]:
-        it = int(np.argmax(gpu_sel[idx[j]] != keys[j]))
-        fails.append({"block": int(idx[j]), "iteration": it,
-                      "oracle_margin": float(margin[j, it]),
-                      "min_margin_before": float(margin[j, :it + 1].min()),
-                      "gpu_key": int(gpu_sel[idx[j], it]), "oracle_key": int(keys[j, it])})
-    return {"blocks": int(len(idx)), "rule_ok": bool(ok.all()), "diverging": int(div.sum()),
-            "max_abs_dg": float(err[same].max()) if same.any() else None, "failures": fails}
+    rows = divergence_report(gpu_sel[idx], keys, margin, top, limit=len(idx))
+    for r in rows:
+        r["block"] = int(idx[r["block"]])
+    res = {"blocks": int(len(idx)), "rule_ok": bool(ok.all()), "diverging": int(div.sum()),
+           "max_abs_dg": float(err[same].max()) if same.any() else None,
+           "floor_over_A0": FLOOR, "diverging_blocks": rows[:20],
+           "failures": [r for r in rows if not r["within_rule"]][:5]}
+    if gpu_coef is not None and len(ref) >= 7:
+        coef_ref, W0 = ref[5], ref[6]
+        d = spectral_drift(gpu_sel[idx], gpu_coef[idx], keys, coef_ref, W0, top, GAMMA)
+        res["drift_max_over_A0"] = float(d.max())
+    return res
 
 
 SMALL_SAMPLE = 4       # oracle-checked blocks per class and variant of the small-size leg
@@ -880,6 +883,7 @@ def main():
     status = st.cpu().numpy()
     out_h = out.cpu().numpy()
     sel_h = sel.cpu().numpy()
+    coef_h = coef.cpu().numpy()
 
     fpb = flops_per_block(T, K)
     kern = float(np.mean(kern_ms)) * 1e-3
@@ -925,7 +929,7 @@ def main():
         result["small_variants"] = small
     if base is not None:
         info, ref = base
-        info["sample_parity"] = sample_parity(ref, out_h, sel_h)
+        info["sample_parity"] = sample_parity(ref, out_h, sel_h, coef_h)
         result["cpu_baseline"] = info
     print(json.dumps(result), flush=True)
 

@@ -280,31 +280,100 @@ def replay(f, known, T: int, rho_hat: float, gamma: float, keys,
     return g, np.array(coef, np.complex128)
 
 
+# Rounding floor of the parity rule, relative to the initial largest class
+# magnitude A0 = |R^(0)|_max of the block.  Two computations of the same
+# iteration in IEEE double precision differ in |R[u]| by their rounding noise
+# (transform, and the accumulated updates); a selection can only swap two
+# classes whose gap is below twice that difference.  Measured on the 1,024-block
+# sample of the 1080p concealment workload (48 x 48 areas, T = 64, K = 200) and
+# bounded again by every parity test (spectral_drift): at most 2.9e-14 A0.
+FLOOR = 1e-13
+
+
 def selection_parity(keys_gpu, keys_ref, margin_ref, tol: float = 1e-6,
-                     top_ref=None, floor: float = 1e-10):
-    """Acceptance rule for a selection sequence computed with other rounding.
+                     top_ref=None, floor: float = FLOOR):
+    """Acceptance rule for a selection sequence computed with other rounding
+    (eq. 9: the class of largest |R_w| is selected).
 
     Iteration nu is "undecided" when the reference gap between the two largest
     class magnitudes, a1 - a2 = margin * a1, is at most tol * a1 (the relative
     rule) or, when ``top_ref`` (a1 per iteration) is given, at most
-    floor * A0 with A0 = a1 of the first iteration: then the residual has
-    decayed to a level where both computations are at rounding noise.  nu* is
-    the first undecided iteration; the sequences must agree before nu* (the
-    whole sequence if there is none).  Returns (ok, diverged): ok[b] is False
-    on a mismatch before nu*; diverged[b] is True when they differ at or after.
+    floor * A0 with A0 = a1 of the first iteration: a gap at the level of the
+    two computations' rounding noise.  nu* is the first undecided iteration;
+    the sequences must agree before nu* (the whole sequence if there is none).
+    Returns (ok, diverged): ok[b] is False on a mismatch before nu*;
+    diverged[b] is True when they differ at or after it.
     """
     keys_gpu = np.atleast_2d(np.asarray(keys_gpu))
     keys_ref = np.atleast_2d(np.asarray(keys_ref))
     margin_ref = np.atleast_2d(np.asarray(margin_ref))
     B, K = keys_ref.shape
-    low = margin_ref <= tol
-    if top_ref is not None and K > 0:
-        top_ref = np.atleast_2d(np.asarray(top_ref))
-        gap = margin_ref * top_ref
-        low = low | (gap <= floor * top_ref[:, :1])
-    nu_star = np.where(low.any(axis=1), low.argmax(axis=1), K)
+    nu_star = undecided_from(margin_ref, tol, top_ref, floor)
     mism = keys_gpu != keys_ref
     first = np.where(mism.any(axis=1), mism.argmax(axis=1), K)
     ok = first >= nu_star
     diverged = ok & (first < K)
     return ok, diverged
+
+
+def undecided_from(margin_ref, tol: float = 1e-6, top_ref=None, floor: float = FLOOR):
+    """nu* per block: the first iteration the rule of :func:`selection_parity`
+    leaves undecided (K if none)."""
+    margin_ref = np.atleast_2d(np.asarray(margin_ref))
+    B, K = margin_ref.shape
+    low = margin_ref <= tol
+    if top_ref is not None and K > 0:
+        top_ref = np.atleast_2d(np.asarray(top_ref))
+        gap = margin_ref * top_ref
+        low = low | (gap <= floor * top_ref[:, :1])
+    return np.where(low.any(axis=1), low.argmax(axis=1), K)
+
+
+def divergence_report(keys_gpu, keys_ref, margin_ref, top_ref, tol: float = 1e-6,
+                      floor: float = FLOOR, limit: int = 50):
+    """Where and why each diverging block leaves the reference sequence: its
+    nu*, its first mismatching iteration, and the reference margin, gap / A0 and
+    a1 / A0 there (at most ``limit`` blocks)."""
+    keys_gpu = np.atleast_2d(np.asarray(keys_gpu))
+    keys_ref = np.atleast_2d(np.asarray(keys_ref))
+    margin_ref = np.atleast_2d(np.asarray(margin_ref))
+    top_ref = np.atleast_2d(np.asarray(top_ref))
+    K = keys_ref.shape[1]
+    nu_star = undecided_from(margin_ref, tol, top_ref, floor)
+    mism = keys_gpu != keys_ref
+    first = np.where(mism.any(axis=1), mism.argmax(axis=1), K)
+    rows = []
+    for b in np.nonzero(first < K)[0][:limit]:
+        f = int(first[b])
+        a0 = float(top_ref[b, 0])
+        rows.append({"block": int(b), "nu_star": int(nu_star[b]), "first_mismatch": f,
+                     "oracle_margin": float(margin_ref[b, f]),
+                     "gap_over_A0": float(margin_ref[b, f] * top_ref[b, f] / a0) if a0 > 0 else 0.0,
+                     "top_over_A0": float(top_ref[b, f] / a0) if a0 > 0 else 0.0,
+                     "within_rule": bool(f >= nu_star[b])})
+    return rows
+
+
+def spectral_drift(keys_gpu, coef_gpu, keys_ref, coef_ref, W0, top_ref, gamma: float):
+    """Largest difference, relative to A0, between two computations of the
+    selected R_w[u] over the iterations where their sequences still agree.
+    With the constant compensation c = gamma R_w[u] / W0 (eqs. 5, 14), so
+    |c_a - c_b| W0 / gamma is that difference.  coef_gpu is complex (B, K) or
+    (B, K, 2) (re, im).  Returns the per-block maximum (0 for a block without a
+    compared iteration or with A0 = 0)."""
+    keys_gpu = np.atleast_2d(np.asarray(keys_gpu))
+    keys_ref = np.atleast_2d(np.asarray(keys_ref))
+    c = np.asarray(coef_gpu)
+    if c.ndim >= 2 and c.shape[-1] == 2 and not np.iscomplexobj(c) and c.ndim == keys_ref.ndim + 1:
+        c = c[..., 0] + 1j * c[..., 1]
+    c = np.atleast_2d(c)
+    cr = np.atleast_2d(np.asarray(coef_ref))
+    top_ref = np.atleast_2d(np.asarray(top_ref))
+    W0 = np.atleast_1d(np.asarray(W0, dtype=np.float64))
+    B, K = keys_ref.shape
+    mism = keys_gpu != keys_ref
+    first = np.where(mism.any(axis=1), mism.argmax(axis=1), K)
+    valid = np.arange(K)[None, :] < first[:, None]
+    a0 = top_ref[:, :1] if K > 0 else np.ones((B, 1))
+    d = np.abs(c - cr) * (W0[:, None] / gamma) / np.where(a0 > 0, a0, np.inf)
+    return np.where(valid, d, 0.0).max(axis=1) if K > 0 else np.zeros(B)

@@ -82,6 +82,17 @@ __device__ __forceinline__ void wave_body(double2* win, Xchg<NW>* xchg, const KP
         run_wave<T, NW, WI, FULL>(R, win, xchg, p, b, lane, gW0);
 }
 
+// Every wave of the workgroup runs wave_body with its own compile-time row
+// range (each wave takes the same barriers in it).
+template <int T, int NW, int WI, int WPT, bool FULL>
+__device__ __forceinline__ void dispatch_wave(int wave, double2* win, Xchg<NW>* xchg, const KParams& p, int b,
+                                              int tid, int lane, const double2* wv, double gW0, int flags_pre,
+                                              int* s_flags) {
+    if (wave == WI) wave_body<T, NW, WI, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, s_flags);
+    if constexpr (WI + 1 < NW)
+        dispatch_wave<T, NW, WI + 1, WPT, FULL>(wave, win, xchg, p, b, tid, lane, wv, gW0, flags_pre, s_flags);
+}
+
 // FULL: the full compensation of eqs. 10-13 instead of eq. 14 (one wavefront
 // per block; gamma is not used).
 template <int T, int NW, bool FULL = false>
@@ -161,10 +172,7 @@ __global__ __launch_bounds__(NW * 64, 2) void fofse_fwd_kernel(KParams p) {
         }
     }
 
-    if (wave == 0) wave_body<T, NW, 0, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 1) if (wave == 1) wave_body<T, NW, 1, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 2) if (wave == 2) wave_body<T, NW, 2, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
-    if constexpr (NW > 3) if (wave == 3) wave_body<T, NW, 3, WPT, FULL>(win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
+    dispatch_wave<T, NW, 0, WPT, FULL>(wave, win, xchg, p, b, tid, lane, wv, gW0, flags_pre, &s_flags);
 
     // parameters out of range: that flag alone (as on every other path)
     const int flags = params_ok ? (s_flags | flags_pre) : FOFSE_BLOCK_BAD_PARAM;

@@ -198,7 +198,9 @@ def test_backward_edge_cases(frame_areas):
 
 def test_autograd_mse_loss(frame_areas):
     """torch.autograd end to end: forward kernel, MSE on B against the true
-    pixels, adjoint kernel; compared with the oracle where the selections agree."""
+    pixels, adjoint kernel.  The adjoint is defined for any fixed selection, so
+    every block is compared with the oracle adjoint of the GPU's own record and
+    loss gradient, and the summed (rho_hat, gamma) gradient is always checked."""
     from paper_2207_01205_amd.autograd import fofse_extrapolate
     A = frame_areas
     sub = slice(400, 432)
@@ -216,23 +218,21 @@ def test_autograd_mse_loss(frame_areas):
     loss.backward()
     torch.cuda.synchronize()
     assert torch.all(status == 0)
-    _, sel, _, _ = plan.extrapolate(a.detach(), rg.detach(), known=k, record=True)
+    # the record of the same forward (deterministic: the same bits as inside
+    # the autograd call) and the loss gradient the backward received
+    out2, sel, _, _ = plan.extrapolate(a.detach(), rg.detach(), known=k, record=True)
+    assert torch.equal(out2, out.detach())
     sel = sel.cpu().numpy()
     f, kn = _support(A.areas[sub], A.known[sub], A.target)
     ref = fofse(f, kn, 64, 0.8, 0.5, 200)
-    ok, _ = selection_parity(sel, ref.keys, ref.margin, 1e-6, top_ref=ref.top)
+    ok, div = selection_parity(sel, ref.keys, ref.margin, 1e-6, top_ref=ref.top)
     assert ok.all()
-    same = np.all(sel == ref.keys, axis=1)
-    assert same.sum() >= 24
-    g_ref = ref.g.reshape(n, -1)[:, tb]
-    gbar_b = 2.0 * (g_ref - A.truth[sub].reshape(n, -1)[:, tb]) / g_ref.size
-    fb, rb, gmb = oracle_adjoints(f[same], kn[same], A.target, 64, 0.8, 0.5, ref.keys[same],
-                                  gbar_b[same])
-    ga = a.grad.cpu().numpy()[same]
-    scale = np.abs(fb).reshape(len(fb), -1).max(axis=1)
-    err = np.abs(ga - fb).reshape(len(fb), -1).max(axis=1)
+    gbar_b = (2.0 * (out.detach() - truth) / out.numel()).cpu().numpy()
+    fb, rb, gmb = oracle_adjoints(f, kn, A.target, 64, 0.8, 0.5, sel, gbar_b)
+    ga = a.grad.cpu().numpy()
+    scale = np.abs(fb).reshape(n, -1).max(axis=1)
+    err = np.abs(ga - fb).reshape(n, -1).max(axis=1)
     assert np.all(err <= 1e-5 * scale), np.max(err / scale)
-    if same.all():
-        np.testing.assert_allclose(rg.grad.cpu().numpy(), [rb.sum(), gmb.sum()], rtol=1e-5)
-    print(f"[gpu] autograd: blocks compared {int(same.sum())}/{n}, max rel dL/df {np.max(err / scale):.2e}",
-          flush=True)
+    np.testing.assert_allclose(rg.grad.cpu().numpy(), [rb.sum(), gmb.sum()], rtol=1e-5)
+    print(f"[gpu] autograd: {n} blocks ({int(div.sum())} diverging from the oracle's selection), "
+          f"max rel dL/df {np.max(err / scale):.2e}", flush=True)

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from oracle.fofse_dft import (canonical_key, canonical_mask, fofse, isotropic_weight,
-                              replay, selection_parity, self_conjugate, synthesize)
+                              replay, selection_parity, self_conjugate, synthesize,
+                              divergence_report, spectral_drift, undecided_from)
 from oracle.ofse_spatial import ofse_spatial
 from paper_2207_01205_amd import synth
 
@@ -272,7 +273,7 @@ def test_selection_parity_rule():
 def test_selection_parity_floor():
     ref = np.array([[0, 0, 0]])
     margin = np.array([[0.5, 0.5, 0.5]])
-    top = np.array([[1e4, 1e-3, 1e-7]])      # gap 5e-4 > 1e-6, then 5e-8 <= 1e-10 * 1e4
+    top = np.array([[1e4, 1e-3, 1e-10]])     # gap 5e-4 > 1e-13 * 1e4, then 5e-11 <= 1e-9
     gpu = np.array([[0, 0, 1]])
     ok, _ = selection_parity(gpu, ref, margin)
     assert not ok[0]
@@ -280,6 +281,34 @@ def test_selection_parity_floor():
     assert ok[0] and div[0]
     ok, _ = selection_parity(np.array([[0, 1, 1]]), ref, margin, top_ref=top)
     assert not ok[0]
+    # a gap above the floor stays decided
+    top2 = np.array([[1e4, 1e-3, 1e-8]])     # 5e-9 > 1e-9
+    ok, _ = selection_parity(gpu, ref, margin, top_ref=top2)
+    assert not ok[0]
+    assert undecided_from(margin, top_ref=top).tolist() == [2]
+    assert undecided_from(margin, top_ref=top2).tolist() == [3]
+
+
+def test_divergence_report_and_drift():
+    """The report names nu*, the first mismatch and the reference margin there;
+    the drift of a perturbed record is the perturbation times W0 / gamma / A0."""
+    f, known, _ = synth.single_block(3)
+    r = fofse(f[None], known[None], 32, 0.8, 0.5, 12)
+    gpu = r.keys.copy()
+    gpu[0, 7] += 1
+    rows = divergence_report(gpu, r.keys, r.margin, r.top)
+    assert len(rows) == 1 and rows[0]["first_mismatch"] == 7
+    assert rows[0]["nu_star"] == 12 and not rows[0]["within_rule"]
+    assert rows[0]["oracle_margin"] == r.margin[0, 7]
+    c = r.coef.copy()
+    c[0, 3] += 1e-9
+    d = spectral_drift(r.keys, c, r.keys, r.coef, r.W0, r.top, 0.5)
+    assert np.isclose(d[0], 1e-9 * r.W0[0] / 0.5 / r.top[0, 0], rtol=1e-6)
+    # iterations after the first mismatch are not compared
+    d2 = spectral_drift(gpu, np.where(np.arange(12) >= 7, c + 1.0, c), r.keys, r.coef, r.W0, r.top, 0.5)
+    assert np.isclose(d2[0], d[0])
+    cc = np.stack([c.real, c.imag], axis=-1)
+    assert np.isclose(spectral_drift(r.keys, cc, r.keys, r.coef, r.W0, r.top, 0.5)[0], d[0])
 
 
 def test_top_magnitude_and_margin_consistent():
