@@ -39,7 +39,8 @@ typedef enum {
     FOFSE_ERR_ARG = 1,          /* invalid argument (NULL, size, range)       */
     FOFSE_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. an FFT size)     */
     FOFSE_ERR_NOMEM = 3,        /* device allocation failed                   */
-    FOFSE_ERR_DEVICE = 4        /* a HIP call or a kernel launch failed       */
+    FOFSE_ERR_DEVICE = 4,       /* a HIP call or a kernel launch failed       */
+    FOFSE_ERR_LIMIT = 5         /* batch beyond a fixed workspace limit       */
 } fofse_status;
 
 /* Per-block status bits written to d_status (0 = block processed normally). */
@@ -187,12 +188,19 @@ fofse_status fofse_set_compensation(fofse_plan plan, int32_t mode);
  *
  * The model on B is synthesised from the selection record, so when d_sel or
  * d_coef is NULL the plan keeps a record of its own (12 B per block and
- * iteration, grown when a larger batch arrives).
+ * iteration).  The grouped path and the DCT basis with per-block masks
+ * (d_known non-NULL) use a plan-owned grouping workspace (about 40 B per
+ * block).  Both grow when a larger batch arrives, to at least twice their
+ * previous size; the buffers they replace stay allocated until fofse_destroy,
+ * so a graph captured before the growth stays valid.  No buffer is allocated
+ * while `stream` is being captured into a graph: a captured call must find the
+ * plan's buffers large enough (make one eager call with at least as many
+ * blocks first).
  *
  * Returns FOFSE_ERR_ARG (NULL plan or required pointer, n_blocks < 0),
- * FOFSE_ERR_NOMEM if a plan-owned buffer (the record above, or the grouped
- * path's workspace of about 20 B per hash slot + 32 B per block) cannot be
- * allocated, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
+ * FOFSE_ERR_NOMEM if a plan-owned buffer cannot be allocated,
+ * FOFSE_ERR_UNSUPPORTED if one would have to grow while the stream is being
+ * captured, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
  * n_blocks == 0 is a no-op.
  */
 fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
@@ -270,14 +278,17 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  * FP64 rounding, and each is deterministic: the same inputs give the same bits,
  * whatever other blocks share the batch.
  *
+ * Plan-owned buffers (the per-block gradients, 16 B per block, used when
+ * d_grad_block is NULL, and the grouped path's workspace) grow as in
+ * fofse_extrapolate_batch, and never while the stream is being captured.
+ *
  * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
  * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
  * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, T exceeds 64, the plan's basis is
  * the DCT (FOFSE_BASIS_DCT has no adjoint) or its compensation is
- * FOFSE_COMP_FULL, FOFSE_ERR_NOMEM if
- * the per-block workspace (16 B per block, used when d_grad_block is NULL) or
- * the grouped path's workspace cannot be allocated, FOFSE_ERR_DEVICE if a
- * launch fails, FOFSE_OK otherwise.
+ * FOFSE_COMP_FULL, or when a plan-owned buffer would have to grow under
+ * stream capture, FOFSE_ERR_NOMEM if a plan-owned buffer cannot be
+ * allocated, FOFSE_ERR_DEVICE if a launch fails, FOFSE_OK otherwise.
  * n_blocks == 0 is a no-op (d_grad_rho_gamma is not written).
  */
 fofse_status fofse_backward(fofse_plan plan, int32_t n_blocks,

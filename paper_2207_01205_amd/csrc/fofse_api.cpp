@@ -30,19 +30,22 @@ struct fofse_plan_s {
     double* d_wtab = nullptr;       // rho_hat ** dist per sample, refreshed per call
     double* d_dwtab = nullptr;      // its derivative in rho_hat (adjoint only)
     // per-block gradients when the caller passes no d_grad_block
-    int gblk_blocks = 0;
+    size_t gblk_bytes = 0;
     double* d_gblk = nullptr;
     // grouped-path workspace, grown on demand (capacity in blocks)
     int ws_blocks = 0;
-    int ws_hsize = 0;
+    size_t ws_bytes = 0;
     void* d_ws = nullptr;
+    // buffers replaced by larger ones: kept until fofse_destroy, since a graph
+    // captured before the growth still refers to them
+    std::vector<void*> retired;
     // profiling: event pairs around the main kernel of the last kRing calls
     bool timing = false;
     hipEvent_t ev_start[256] = {};
     hipEvent_t ev_stop[256] = {};
     long long n_timed = 0;
     // selection record used when the caller passes no d_sel / d_coef
-    size_t rec_blocks = 0;
+    size_t rec_sel_bytes = 0, rec_coef_bytes = 0;
     int32_t* d_rec_sel = nullptr;
     double* d_rec_coef = nullptr;
 };
@@ -95,6 +98,7 @@ void free_plan(fofse_plan p) {
     if (p->d_dwtab) (void)hipFree(p->d_dwtab);
     if (p->d_gblk) (void)hipFree(p->d_gblk);
     if (p->d_dct_cos) (void)hipFree(p->d_dct_cos);
+    for (void* q : p->retired) (void)hipFree(q);
     delete p;
 }
 
@@ -105,24 +109,47 @@ bool grouped_supported(const fofse_plan_s* p) {
            p->N <= 64;
 }
 
-// Workspace of the grouped path for n blocks: hash table of hsize slots
-// (key 8 B, representative, count, first item: 4 B each), per-block class and
-// position, per-item block list, size and class, three counters.
-fofse_status ensure_workspace(fofse_plan p, int n, fofse::GroupArgs& g) {
+// True when the stream is being captured into a graph (no allocation may be
+// recorded then).
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Grows a plan-owned device buffer to at least `bytes` (to twice its capacity
+// at least, so that growth is rare).  The replaced buffer stays allocated until
+// fofse_destroy: a graph captured before the growth still refers to it.  Under
+// stream capture no buffer is allocated: FOFSE_ERR_UNSUPPORTED.
+fofse_status grow_buffer(fofse_plan p, void** buf, size_t* cap, size_t bytes, hipStream_t st) {
+    if (bytes <= *cap) return FOFSE_OK;
+    if (capturing(st)) return FOFSE_ERR_UNSUPPORTED;
+    const size_t nb = bytes > 2 * *cap ? bytes : 2 * *cap;
+    void* q = nullptr;
+    if (hipMalloc(&q, nb) != hipSuccess) return FOFSE_ERR_NOMEM;
+    if (*buf) p->retired.push_back(*buf);
+    *buf = q;
+    *cap = nb;
+    return FOFSE_OK;
+}
+
+int hash_slots(int n) {
     int hsize = 64;
     while (hsize < 2 * n) hsize <<= 1;
-    if (n > p->ws_blocks || hsize > p->ws_hsize) {
-        if (p->d_ws) (void)hipFree(p->d_ws);
-        p->d_ws = nullptr;
-        p->ws_blocks = p->ws_hsize = 0;
-        const size_t bytes = (size_t)hsize * 20 + (size_t)n * (8 + 4 * fofse::kGroup + 8) + 64;
-        if (hipMalloc(&p->d_ws, bytes) != hipSuccess) return FOFSE_ERR_NOMEM;
-        p->ws_blocks = n;
-        p->ws_hsize = hsize;
-    }
-    hsize = p->ws_hsize;
-    const int cap = p->ws_blocks;
-    char* c = (char*)p->d_ws;
+    return hsize;
+}
+
+// Workspace of the grouped path for a capacity of n blocks: hash table of
+// hsize slots (key 8 B, representative, count, first item: 4 B each), per-block
+// class and position, per-item block list, size and class, three counters.
+size_t workspace_bytes_for(int n) {
+    return (size_t)hash_slots(n) * 20 + (size_t)n * (8 + 4 * fofse::kGroup + 8) + 64;
+}
+
+// Lays the workspace for a capacity of cap blocks out from base (256-byte
+// aligned).
+void carve_workspace(void* base, int cap, fofse::GroupArgs& g) {
+    const int hsize = hash_slots(cap);
+    char* c = (char*)base;
     g.hsize = hsize;
     g.hmask = (uint32_t)(hsize - 1);
     g.ht_key = (unsigned long long*)c; c += (size_t)hsize * 8;
@@ -136,26 +163,143 @@ fofse_status ensure_workspace(fofse_plan p, int n, fofse::GroupArgs& g) {
     g.item_cls = (int*)c; c += (size_t)cap * 4;
     g.n_single = (int*)c; c += 16;
     g.counts = (int*)c;
+}
+
+// The grouping workspace for n blocks: the caller's (ws), else the plan's,
+// grown on demand.
+fofse_status ensure_workspace(fofse_plan p, int n, fofse::GroupArgs& g, const fofse::Workspace* ws,
+                              hipStream_t st) {
+    if (ws) {
+        if (workspace_bytes_for(n) > ws->bytes) return FOFSE_ERR_LIMIT;
+        carve_workspace(ws->base, n, g);
+        return FOFSE_OK;
+    }
+    if (n > p->ws_blocks) {
+        const int cap = n > 2 * p->ws_blocks ? n : 2 * p->ws_blocks;
+        if (capturing(st)) return FOFSE_ERR_UNSUPPORTED;
+        void* q = nullptr;
+        if (hipMalloc(&q, workspace_bytes_for(cap)) != hipSuccess) return FOFSE_ERR_NOMEM;
+        if (p->d_ws) p->retired.push_back(p->d_ws);
+        p->d_ws = q;
+        p->ws_blocks = cap;
+        p->ws_bytes = workspace_bytes_for(cap);
+    }
+    carve_workspace(p->d_ws, p->ws_blocks, g);
     return FOFSE_OK;
 }
 
 // Record of n blocks (K keys, K coefficients each) owned by the plan.
-fofse_status ensure_record(fofse_plan p, int n) {
-    if ((size_t)n <= p->rec_blocks) return FOFSE_OK;
-    if (p->d_rec_sel) (void)hipFree(p->d_rec_sel);
-    if (p->d_rec_coef) (void)hipFree(p->d_rec_coef);
-    p->d_rec_sel = nullptr;
-    p->d_rec_coef = nullptr;
-    p->rec_blocks = 0;
+fofse_status ensure_record(fofse_plan p, int n, hipStream_t st) {
     const size_t k = p->K > 0 ? (size_t)p->K : 1;
-    if (hipMalloc(&p->d_rec_sel, (size_t)n * k * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&p->d_rec_coef, (size_t)n * k * 2 * sizeof(double)) != hipSuccess)
-        return FOFSE_ERR_NOMEM;
-    p->rec_blocks = (size_t)n;
-    return FOFSE_OK;
+    fofse_status s = grow_buffer(p, (void**)&p->d_rec_sel, &p->rec_sel_bytes, (size_t)n * k * sizeof(int32_t), st);
+    if (s != FOFSE_OK) return s;
+    return grow_buffer(p, (void**)&p->d_rec_coef, &p->rec_coef_bytes, (size_t)n * k * 2 * sizeof(double), st);
 }
 
 }  // namespace
+
+namespace fofse {
+
+// fofse_extrapolate_batch with an optional caller-supplied grouping workspace
+// (ws; the record must then be the caller's).  Without one, plan-owned
+// buffers are grown on demand.
+fofse_status extrapolate_impl(fofse_plan p, int32_t n_blocks, const float* d_areas, const uint8_t* d_known,
+                              const double* d_rho_gamma, float* d_out, int32_t* d_sel, double* d_coef,
+                              int32_t* d_status, void* stream, const Workspace* ws) {
+    if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
+    if (n_blocks == 0) return FOFSE_OK;
+    if (!d_areas || !d_rho_gamma || !d_out) return FOFSE_ERR_ARG;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return FOFSE_ERR_DEVICE;
+    KParams k{};
+    k.n_blocks = n_blocks;
+    k.T = p->T; k.M = p->M; k.N = p->N; k.K = p->K; k.nB = p->nB;
+    k.areas = d_areas;
+    k.known = d_known;
+    k.target = p->d_target;
+    k.bpix = p->d_bpix;
+    k.bidx = p->d_bidx;
+    k.b_m0 = p->b_m0; k.b_n0 = p->b_n0; k.b_h = p->b_h; k.b_w = p->b_w;
+    k.rho_gamma = d_rho_gamma;
+    k.twiddle = p->d_twiddle;
+    k.wtab = p->d_wtab;
+    k.out = d_out;
+    k.sel = d_sel;
+    k.coef = d_coef;
+    k.status = d_status;
+    k.waves = p->waves;
+    hipStream_t st = (hipStream_t)stream;
+    if (!d_sel || !d_coef) {
+        if (ws) return FOFSE_ERR_ARG;            // a caller-supplied workspace holds no record
+        const fofse_status rs = ensure_record(p, n_blocks, st);
+        if (rs != FOFSE_OK) return rs;
+        if (!d_sel) k.sel = p->d_rec_sel;
+        if (!d_coef) k.coef = p->d_rec_coef;
+    }
+    if (p->basis == FOFSE_BASIS_DCT && p->comp != FOFSE_COMP_CONSTANT) return FOFSE_ERR_UNSUPPORTED;
+    if (p->basis == FOFSE_BASIS_DCT) {
+        Timing tm{};
+        if (p->timing) {
+            const int i = (int)(p->n_timed % kRing);
+            tm.start = p->ev_start[i];
+            tm.stop = p->ev_stop[i];
+            ++p->n_timed;
+        }
+        GroupArgs g{};
+        g.MN = p->M * p->N;
+        g.known = d_known;
+        g.target = p->d_target;
+        g.direct = d_known == nullptr;
+        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        if (!g.direct) {
+            const fofse_status wst = ensure_workspace(p, n_blocks, g, ws, st);
+            if (wst != FOFSE_OK) return wst;
+            if (launch_clear(g, st) != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        const hipError_t e = launch_dct(k, g, p->d_dct_cos, p->n_cu, st, tm);
+        return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
+    }
+    // the full compensation: grouped organisation at T = 64, one wavefront per
+    // block at T = 16 and 32
+    const bool full = p->comp == FOFSE_COMP_FULL;
+    bool grouped = full && p->T == 64;
+    if (p->path == FOFSE_PATH_GROUPED) grouped = true;
+    else if (p->path == FOFSE_PATH_AUTO)
+        grouped = grouped || (grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu);
+    hipError_t e;
+    Timing tm{};
+    if (p->timing) {
+        const int i = (int)(p->n_timed % kRing);
+        tm.start = p->ev_start[i];
+        tm.stop = p->ev_stop[i];
+        ++p->n_timed;
+    }
+    if (grouped) {
+        GroupArgs g{};
+        g.MN = p->M * p->N;
+        g.known = d_known;
+        g.target = p->d_target;
+        g.direct = d_known == nullptr;
+        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        if (!g.direct) {
+            const fofse_status wst = ensure_workspace(p, n_blocks, g, ws, st);
+            if (wst != FOFSE_OK) return wst;
+            e = launch_clear(g, st);
+            if (e != hipSuccess) return FOFSE_ERR_DEVICE;
+        }
+        e = p->T == 128 ? launch_grouped128(k, g, p->n_cu, st, tm)
+                        : launch_grouped(k, g, p->n_cu, st, tm, full);
+    } else {
+        e = launch_forward(k, st, tm, full);
+    }
+    return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
+}
+
+int plan_device(fofse_plan p) { return p ? p->device : -1; }
+
+size_t grouping_workspace_bytes(int n_blocks) { return workspace_bytes_for(n_blocks); }
+
+}  // namespace fofse
 
 extern "C" {
 
@@ -166,6 +310,7 @@ const char* fofse_status_str(fofse_status s) {
         case FOFSE_ERR_UNSUPPORTED: return "unsupported configuration";
         case FOFSE_ERR_NOMEM: return "device allocation failed";
         case FOFSE_ERR_DEVICE: return "HIP runtime or launch failure";
+        case FOFSE_ERR_LIMIT: return "batch exceeds a fixed workspace limit";
     }
     return "unknown status";
 }
@@ -322,92 +467,8 @@ fofse_status fofse_extrapolate_batch(fofse_plan p, int32_t n_blocks, const float
                                      const uint8_t* d_known, const double* d_rho_gamma,
                                      float* d_out, int32_t* d_sel, double* d_coef,
                                      int32_t* d_status, void* stream) {
-    if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
-    if (n_blocks == 0) return FOFSE_OK;
-    if (!d_areas || !d_rho_gamma || !d_out) return FOFSE_ERR_ARG;
-    DeviceGuard guard(p->device);
-    if (!guard.ok) return FOFSE_ERR_DEVICE;
-    fofse::KParams k{};
-    k.n_blocks = n_blocks;
-    k.T = p->T; k.M = p->M; k.N = p->N; k.K = p->K; k.nB = p->nB;
-    k.areas = d_areas;
-    k.known = d_known;
-    k.target = p->d_target;
-    k.bpix = p->d_bpix;
-    k.bidx = p->d_bidx;
-    k.b_m0 = p->b_m0; k.b_n0 = p->b_n0; k.b_h = p->b_h; k.b_w = p->b_w;
-    k.rho_gamma = d_rho_gamma;
-    k.twiddle = p->d_twiddle;
-    k.wtab = p->d_wtab;
-    k.out = d_out;
-    k.sel = d_sel;
-    k.coef = d_coef;
-    k.status = d_status;
-    k.waves = p->waves;
-    if (!d_sel || !d_coef) {
-        const fofse_status rs = ensure_record(p, n_blocks);
-        if (rs != FOFSE_OK) return rs;
-        if (!d_sel) k.sel = p->d_rec_sel;
-        if (!d_coef) k.coef = p->d_rec_coef;
-    }
-    hipStream_t st = (hipStream_t)stream;
-    if (p->basis == FOFSE_BASIS_DCT && p->comp != FOFSE_COMP_CONSTANT) return FOFSE_ERR_UNSUPPORTED;
-    if (p->basis == FOFSE_BASIS_DCT) {
-        fofse::Timing tm{};
-        if (p->timing) {
-            const int i = (int)(p->n_timed % kRing);
-            tm.start = p->ev_start[i];
-            tm.stop = p->ev_stop[i];
-            ++p->n_timed;
-        }
-        fofse::GroupArgs g{};
-        g.MN = p->M * p->N;
-        g.known = d_known;
-        g.target = p->d_target;
-        g.direct = d_known == nullptr;
-        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
-        if (!g.direct) {
-            const fofse_status ws = ensure_workspace(p, n_blocks, g);
-            if (ws != FOFSE_OK) return ws;
-            if (fofse::launch_clear(g, st) != hipSuccess) return FOFSE_ERR_DEVICE;
-        }
-        const hipError_t e = fofse::launch_dct(k, g, p->d_dct_cos, p->n_cu, st, tm);
-        return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
-    }
-    // the full compensation: grouped organisation at T = 64, one wavefront per
-    // block at T = 16 and 32
-    const bool full = p->comp == FOFSE_COMP_FULL;
-    bool grouped = full && p->T == 64;
-    if (p->path == FOFSE_PATH_GROUPED) grouped = true;
-    else if (p->path == FOFSE_PATH_AUTO)
-        grouped = grouped || (grouped_supported(p) && n_blocks >= kGroupedMinBlocksPerCu * p->n_cu);
-    hipError_t e;
-    fofse::Timing tm{};
-    if (p->timing) {
-        const int i = (int)(p->n_timed % kRing);
-        tm.start = p->ev_start[i];
-        tm.stop = p->ev_stop[i];
-        ++p->n_timed;
-    }
-    if (grouped) {
-        fofse::GroupArgs g{};
-        g.MN = p->M * p->N;
-        g.known = d_known;
-        g.target = p->d_target;
-        g.direct = d_known == nullptr;
-        g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
-        if (!g.direct) {
-            const fofse_status ws = ensure_workspace(p, n_blocks, g);
-            if (ws != FOFSE_OK) return ws;
-            e = fofse::launch_clear(g, st);
-            if (e != hipSuccess) return FOFSE_ERR_DEVICE;
-        }
-        e = p->T == 128 ? fofse::launch_grouped128(k, g, p->n_cu, st, tm)
-                        : fofse::launch_grouped(k, g, p->n_cu, st, tm, full);
-    } else {
-        e = fofse::launch_forward(k, st, tm, full);
-    }
-    return e == hipSuccess ? FOFSE_OK : FOFSE_ERR_DEVICE;
+    return fofse::extrapolate_impl(p, n_blocks, d_areas, d_known, d_rho_gamma, d_out, d_sel, d_coef, d_status,
+                                   stream, nullptr);
 }
 
 fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas,
@@ -422,16 +483,12 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         return FOFSE_ERR_UNSUPPORTED;
     DeviceGuard guard(p->device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
     double* blk = d_grad_block;
     if (!blk) {
-        if (n_blocks > p->gblk_blocks) {
-            if (p->d_gblk) (void)hipFree(p->d_gblk);
-            p->d_gblk = nullptr;
-            p->gblk_blocks = 0;
-            if (hipMalloc(&p->d_gblk, (size_t)n_blocks * 2 * sizeof(double)) != hipSuccess)
-                return FOFSE_ERR_NOMEM;
-            p->gblk_blocks = n_blocks;
-        }
+        const fofse_status gs = grow_buffer(p, (void**)&p->d_gblk, &p->gblk_bytes,
+                                            (size_t)n_blocks * 2 * sizeof(double), st);
+        if (gs != FOFSE_OK) return gs;
         blk = p->d_gblk;
     }
     fofse::KParams wp{};
@@ -464,7 +521,6 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         tm.stop = p->ev_stop[i];
         ++p->n_timed;
     }
-    hipStream_t st = (hipStream_t)stream;
     // grouped adjoint: same rule as the forward, for K up to its register capacity
     const bool grouped_ok = p->T == 64 && grouped_supported(p) && p->K <= fofse::kGroupBackwardMaxK;
     bool grouped = false;
@@ -479,8 +535,8 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         g.direct = d_known == nullptr;
         g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
         if (!g.direct) {
-            const fofse_status ws = ensure_workspace(p, n_blocks, g);
-            if (ws != FOFSE_OK) return ws;
+            const fofse_status wst = ensure_workspace(p, n_blocks, g, nullptr, st);
+            if (wst != FOFSE_OK) return wst;
             e = fofse::launch_clear(g, st);
             if (e != hipSuccess) return FOFSE_ERR_DEVICE;
         }

@@ -95,6 +95,23 @@ struct GroupArgs {
     int* item_cls;                    // [n] class of the item
 };
 
+// Device memory a caller lends to a call for the grouping workspace (the
+// no-allocation entry point's fixed scratch).
+struct Workspace {
+    void* base;          // 256-byte aligned device address
+    size_t bytes;        // capacity
+};
+
+// fofse_extrapolate_batch with an optional workspace in place of the plan's
+// (ws non-null: d_sel and d_coef are required, nothing is allocated).
+fofse_status extrapolate_impl(fofse_plan p, int32_t n_blocks, const float* d_areas, const uint8_t* d_known,
+                              const double* d_rho_gamma, float* d_out, int32_t* d_sel, double* d_coef,
+                              int32_t* d_status, void* stream, const Workspace* ws);
+// HIP device of a plan (-1 for NULL).
+int plan_device(fofse_plan p);
+// Bytes of grouping workspace a batch of n blocks uses.
+size_t grouping_workspace_bytes(int n_blocks);
+
 // Optional events recorded on the stream right before and after the main
 // iteration kernel (null: not recorded).
 struct Timing {

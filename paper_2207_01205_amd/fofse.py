@@ -22,6 +22,7 @@ FOFSE_ERR_ARG = 1
 FOFSE_ERR_UNSUPPORTED = 2
 FOFSE_ERR_NOMEM = 3
 FOFSE_ERR_DEVICE = 4
+FOFSE_ERR_LIMIT = 5
 
 FOFSE_BLOCK_NO_SUPPORT = 1
 FOFSE_BLOCK_NONFINITE = 2

@@ -32,8 +32,8 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_status_strings():
-    for st in range(5):
-        assert F.fofse_status_str(st)
+    for st in range(6):
+        assert F.fofse_status_str(st) != "unknown status"
     assert F.fofse_status_str(99) == "unknown status"
 
 

@@ -128,3 +128,61 @@ def test_dct_basis_graph_replays_match_eager():
             assert np.array_equal(x, y), f"replay differs from eager in {name} at rho={rho} gamma={gamma}"
         assert np.all(eager[3] == 0)
         del junk
+
+
+def test_plan_buffers_survive_growth_after_capture():
+    """A graph captured at one batch size keeps working after an eager call
+    with a larger batch grows the plan's buffers (the replaced buffers stay
+    allocated); a captured call that would have to grow a buffer is refused
+    instead of allocating under capture."""
+    from paper_2207_01205_amd import fofse as F
+    A = synth.frame_concealment(8, 9)
+    dev = torch.device("cuda", 0)
+    plan = F.Plan(48, 48, 64, 60, A.target)
+    plan.set_path(F.FOFSE_PATH_GROUPED)
+    a = torch.from_numpy(A.areas[:600].copy()).to(dev)
+    k = torch.from_numpy(A.known[:600].copy()).to(dev)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    out = torch.empty((600, plan.nB), dtype=torch.float32, device=dev)
+
+    def call(n, s):
+        # no record: the plan's own record and grouping workspace are used
+        F.fofse_extrapolate_batch(plan.handle, n, a.data_ptr(), k.data_ptr(), rg.data_ptr(),
+                                  out.data_ptr(), 0, 0, 0, s)
+
+    print("[gpu] capture, then growth of the plan's buffers", flush=True)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        call(40, side.cuda_stream)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    eager40 = out[:40].clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call(40, torch.cuda.current_stream(dev).cuda_stream)
+    torch.cuda.synchronize()
+    call(600, torch.cuda.current_stream(dev).cuda_stream)      # grows record and workspace
+    torch.cuda.synchronize()
+    eager600 = out.clone()
+    for _ in range(3):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[:40], eager40)
+    assert torch.equal(eager600[:40], eager40)
+    del graph
+    # growth needed under capture: refused, nothing enqueued
+    plan2 = F.Plan(48, 48, 64, 60, A.target)
+    plan2.set_path(F.FOFSE_PATH_GROUPED)
+    g2 = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.graph(g2):
+        try:
+            F.fofse_extrapolate_batch(plan2.handle, 40, a.data_ptr(), k.data_ptr(), rg.data_ptr(),
+                                      out.data_ptr(), 0, 0, 0, torch.cuda.current_stream(dev).cuda_stream)
+        except F.FofseError as e:
+            err = e
+    torch.cuda.synchronize()
+    assert err is not None and err.status == F.FOFSE_ERR_UNSUPPORTED
+    del g2

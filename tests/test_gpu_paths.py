@@ -76,8 +76,10 @@ def oracle_dft(areas, known, target, T, rho, gamma, K):
             "gamma": gamma}
 
 
-def oracle_ofse(areas, known, target, T, rho, K):
+def oracle_ofse(areas, known, target, T, rho, K, scale=1.0):
+    """The OFSE oracle on the float32 inputs the GPU sees, times ``scale``."""
     f, kn = _support(areas, known, target)
+    f = f * scale
     res = [ofse_full(np.where(kn[b] != 0, f[b], 0.0), kn[b], T, rho, K) for b in range(len(f))]
     return {key: np.stack([r[key] for r in res]) for key in ("g", "keys", "coef", "margin", "top")}
 
@@ -95,7 +97,7 @@ def ofse_rounding_spread(areas, known, target, T, rho, K, ref):
     sc = np.zeros(len(areas))
     sg = np.zeros(len(areas))
     for alpha in (1.0 + 2.0 ** -30, 1.0 - 3.0 * 2.0 ** -31):
-        r = oracle_ofse(np.asarray(areas, np.float32).astype(np.float64) * alpha, known, target, T, rho, K)
+        r = oracle_ofse(areas, known, target, T, rho, K, scale=alpha)
         same = np.all(r["keys"] == ref["keys"], axis=1)
         dc = np.abs(r["coef"] / alpha - ref["coef"]).max(axis=1) / np.abs(ref["coef"]).max(axis=1)
         dg = np.abs(r["g"] / alpha - ref["g"]).reshape(len(areas), -1).max(axis=1)
