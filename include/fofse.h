@@ -40,7 +40,8 @@ typedef enum {
     FOFSE_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. an FFT size)     */
     FOFSE_ERR_NOMEM = 3,        /* device allocation failed                   */
     FOFSE_ERR_DEVICE = 4,       /* a HIP call or a kernel launch failed       */
-    FOFSE_ERR_LIMIT = 5         /* batch beyond a fixed workspace limit       */
+    FOFSE_ERR_LIMIT = 5         /* batch beyond the fixed scratch of
+                                   fofse_extrapolate_batch_noalloc            */
 } fofse_status;
 
 /* Per-block status bits written to d_status (0 = block processed normally). */
@@ -195,7 +196,7 @@ fofse_status fofse_set_compensation(fofse_plan plan, int32_t mode);
  * so a graph captured before the growth stays valid.  No buffer is allocated
  * while `stream` is being captured into a graph: a captured call must find the
  * plan's buffers large enough (make one eager call with at least as many
- * blocks first).
+ * blocks first), or use fofse_extrapolate_batch_noalloc.
  *
  * Returns FOFSE_ERR_ARG (NULL plan or required pointer, n_blocks < 0),
  * FOFSE_ERR_NOMEM if a plan-owned buffer cannot be allocated,
@@ -208,6 +209,33 @@ fofse_status fofse_extrapolate_batch(fofse_plan plan, int32_t n_blocks,
                                      const double* d_rho_gamma, float* d_out,
                                      int32_t* d_sel, double* d_coef,
                                      int32_t* d_status, void* stream);
+
+/*
+ * fofse_extrapolate_batch for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, meaning and results (the same kernels, the same
+ * bits) as fofse_extrapolate_batch, with two differences:
+ *   - d_sel and d_coef are required (the record the model is synthesised from
+ *     is the caller's);
+ *   - n_blocks is at most FOFSE_NOALLOC_MAX_BLOCKS.
+ * The grouping workspace lives in a fixed 5 MiB device array of the library,
+ * one per device, held from the first call on that device until the process
+ * ends.  Every call on a device shares it: calls that overlap on one device
+ * (concurrent streams, or several host threads) race and give undefined
+ * results.  The plan, and with the DCT basis its cosine table
+ * (fofse_set_basis), are created beforehand; the call allocates nothing.
+ * Returns FOFSE_ERR_LIMIT for n_blocks > FOFSE_NOALLOC_MAX_BLOCKS,
+ * FOFSE_ERR_ARG for a NULL plan, n_blocks < 0 or a NULL required pointer
+ * (d_areas, d_rho_gamma, d_out, d_sel, d_coef), FOFSE_ERR_DEVICE if the
+ * array's address cannot be obtained or a launch fails, otherwise as
+ * fofse_extrapolate_batch.  n_blocks == 0 is a no-op.
+ */
+#define FOFSE_NOALLOC_MAX_BLOCKS 65536
+fofse_status fofse_extrapolate_batch_noalloc(fofse_plan plan, int32_t n_blocks,
+                                             const float* d_areas, const uint8_t* d_known,
+                                             const double* d_rho_gamma, float* d_out,
+                                             int32_t* d_sel, double* d_coef,
+                                             int32_t* d_status, void* stream);
 
 /*
  * Wavefronts per block of the split path (FOFSE_PATH_SPLIT, and AUTO when it

@@ -310,7 +310,7 @@ const char* fofse_status_str(fofse_status s) {
         case FOFSE_ERR_UNSUPPORTED: return "unsupported configuration";
         case FOFSE_ERR_NOMEM: return "device allocation failed";
         case FOFSE_ERR_DEVICE: return "HIP runtime or launch failure";
-        case FOFSE_ERR_LIMIT: return "batch exceeds a fixed workspace limit";
+        case FOFSE_ERR_LIMIT: return "batch exceeds the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }

@@ -40,11 +40,12 @@ FOFSE_COMP_FULL = 1
 
 EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves",
             "fofse_set_basis", "fofse_set_compensation",
-            "fofse_extrapolate_batch",
+            "fofse_extrapolate_batch", "fofse_extrapolate_batch_noalloc",
             "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
             "fofse_status_str")
 
 BACKWARD_MAX_K = 2048
+NOALLOC_MAX_BLOCKS = 65536
 
 
 class FofseError(RuntimeError):
@@ -86,6 +87,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_set_compensation.restype = ctypes.c_int
     L.fofse_extrapolate_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fofse_extrapolate_batch.restype = ctypes.c_int
+    L.fofse_extrapolate_batch_noalloc.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fofse_extrapolate_batch_noalloc.restype = ctypes.c_int
     L.fofse_backward.argtypes = [vp, ctypes.c_int32] + [vp] * 10
     L.fofse_backward.restype = ctypes.c_int
     L.fofse_set_timing.argtypes = [vp, ctypes.c_int32]
@@ -160,6 +163,18 @@ def fofse_extrapolate_batch(plan: int, n_blocks: int, d_areas: int, d_known: int
                                                 d_status or None, stream or None)
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_extrapolate_batch")
+
+
+def fofse_extrapolate_batch_noalloc(plan: int, n_blocks: int, d_areas: int, d_known: int,
+                                    d_rho_gamma: int, d_out: int, d_sel: int, d_coef: int,
+                                    d_status: int, stream: int) -> None:
+    """Raw call with device addresses (ints, 0 for NULL); raises FofseError."""
+    st = load_library().fofse_extrapolate_batch_noalloc(plan, int(n_blocks), d_areas or None,
+                                                        d_known or None, d_rho_gamma or None,
+                                                        d_out or None, d_sel or None, d_coef or None,
+                                                        d_status or None, stream or None)
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_extrapolate_batch_noalloc")
 
 
 def fofse_backward(plan: int, n_blocks: int, d_areas: int, d_known: int, d_rho_gamma: int,

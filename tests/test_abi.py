@@ -50,6 +50,7 @@ def test_null_arguments_rejected_without_gpu():
     for g in bad:
         assert L.fofse_create(ctypes.byref(g), 0, ctypes.byref(out)) == F.FOFSE_ERR_ARG
     assert L.fofse_extrapolate_batch(None, 1, None, None, None, None, None, None, None, None) == F.FOFSE_ERR_ARG
+    assert L.fofse_extrapolate_batch_noalloc(None, 1, *([None] * 8)) == F.FOFSE_ERR_ARG
     assert L.fofse_target_count(None) == 0
     assert L.fofse_set_path(None, 0) == F.FOFSE_ERR_ARG
     assert L.fofse_set_waves(None, 2) == F.FOFSE_ERR_ARG
