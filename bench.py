@@ -46,18 +46,36 @@ TRAFFIC = {"sources_sha256_16": "efec79943d9045a7", "blocks": 12864,
            "fetch_kib": 91509.2, "write_kib": 67624.6, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
+# FP64 instruction counters of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU_FMA_F64
+# SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64), mean per dispatch on the same batch.
+COUNTERS = {"sources_sha256_16": "", "blocks": 12864, "flop": None}
+
+
 def measured_traffic(n_blocks: int):
     """HBM bytes per launch of the main forward kernel, or None when the kernel
     sources or the batch differ from those the counters were taken on."""
+    if not _sources_match(TRAFFIC, n_blocks):
+        return None
+    kib = TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]
+    return kib * 1024.0
+
+
+def measured_counter_flop(n_blocks: int):
+    """FP64 FLOP per launch of the main forward kernel from its rocprofv3
+    counters (64 lanes x (ADD_F64 + MUL_F64 + 2 FMA_F64) wave instructions),
+    or None when the kernel sources or the batch differ from those measured."""
+    if COUNTERS.get("flop") is None or not _sources_match(COUNTERS, n_blocks):
+        return None
+    return COUNTERS["flop"]
+
+
+def _sources_match(rec, n_blocks: int) -> bool:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2207_01205_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != TRAFFIC["sources_sha256_16"] or n_blocks != TRAFFIC["blocks"]:
-        return None
-    kib = TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]
-    return kib * 1024.0
+    return h.hexdigest()[:16] == rec["sources_sha256_16"] and n_blocks == rec["blocks"]
 
 
 def flops_per_block(T: int, K: int) -> float:
@@ -66,6 +84,16 @@ def flops_per_block(T: int, K: int) -> float:
     T x T real FFTs at 2.5 T^2 log2(T^2) each (forward transform, synthesis)."""
     classes = T * T // 2 + 2
     return K * 19.0 * classes + 2 * 2.5 * T * T * np.log2(T * T)
+
+
+def executed_flops_per_block(T: int, K: int) -> float:
+    """FP64 operations the forward kernel's iteration actually issues per block
+    (the loop of the general, complex-W form): per class |R|^2 (a multiply and
+    a fused multiply-add, 3 FLOP) and the update as two complex sums of the two
+    W reads followed by four fused multiply-adds (4 + 8 = 12 FLOP), 15 in all
+    against the 19 credited; the two transforms as credited."""
+    classes = T * T // 2 + 2
+    return K * 15.0 * classes + 2 * 2.5 * T * T * np.log2(T * T)
 
 
 def adjoint_flops_per_block(T: int, K: int, nB: int) -> float:
@@ -181,7 +209,7 @@ def cpu_baseline(areas, known, target, n_sample: int, workers: int):
         "value": n_sample / dt, "unit": "blocks/s", "cores": workers, "kind": "oracle",
         "sample": f"{n_sample} seeded blocks of the same batch (FP64 NumPy DFT-domain oracle, "
                   f"{workers} processes, {dt:.1f} s)",
-        "cpu_model": _cpu_model(),
+        "host": _host_info(workers),
     }
     return info, (idx, g, keys, margin, top, coef, W0)
 
@@ -458,6 +486,72 @@ def run_small_variants(classes, args, dev):
     return out_all
 
 
+def run_single_block(args, dev):
+    """The single-block configuration: one 32 x 32 area (seed 0 of the
+    single-block generator, 16 x 16 centred missing block), T = 32, K = 100,
+    rho_hat 0.8, gamma 0.5.  One workgroup runs it, so the figure of merit is
+    latency: the whole call (weights, iteration kernel, synthesis) by HIP events
+    around each call, and the iteration kernel alone, for every wavefront count
+    of the split path; the rate is put against one compute unit's share of the
+    FP64 peak.  The oracle's selection and output for the block are checked."""
+    import torch
+    from oracle.fofse_dft import fofse, selection_parity
+    from paper_2207_01205_amd import fofse as F
+    from paper_2207_01205_amd import synth
+    from paper_2207_01205_amd.autotune import SPLIT_WAVES
+    f, known, target = synth.single_block(0)
+    T1, K1 = 32, 100
+    a = torch.from_numpy(f.astype(np.float32)[None]).to(dev)
+    rg = torch.tensor([RHO, GAMMA], dtype=torch.float64, device=dev)
+    ref = fofse(f.astype(np.float32).astype(np.float64), known, T1, RHO, GAMMA, K1)
+    fpb = flops_per_block(T1, K1)
+    cu_peak = FP64_VECTOR_PEAK / 256
+    stream = torch.cuda.current_stream(dev)
+    res = {"workload": "single 32x32 block, 16x16 centred missing block, T=32, K=100, rho=0.8, gamma=0.5 "
+                       "(one workgroup)", "flop_per_block": fpb, "by_waves": {}}
+    reps = 50
+    for w in SPLIT_WAVES[T1]:
+        plan = F.Plan(32, 32, T1, K1, target, device=0)
+        plan.set_path(F.FOFSE_PATH_SPLIT)
+        plan.set_waves(w)
+        out, sel, coef, st = plan.extrapolate(a, rg, record=True)
+        torch.cuda.synchronize()
+        ok, _ = selection_parity(sel.cpu().numpy(), ref.keys[None], ref.margin[None], top_ref=ref.top[None])
+        err = float(np.abs(out.cpu().numpy()[0] - ref.g.reshape(-1)[target.reshape(-1) == 1]).max())
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        F.fofse_set_timing(plan.handle, True)
+        for i in range(reps):
+            ev[2 * i].record(stream)
+            plan.extrapolate(a, rg, out=out, status=False)
+            ev[2 * i + 1].record(stream)
+            torch.cuda.synchronize()
+        kern = F.fofse_kernel_times(plan.handle, reps)
+        F.fofse_set_timing(plan.handle, False)
+        call_ms = float(np.median([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+        kern_ms = float(np.median(kern))
+        res["by_waves"][f"split/{w}"] = {
+            "call_latency_ms": call_ms, "kernel_ms": kern_ms,
+            "kernel_tflops": fpb / (kern_ms * 1e-3) / 1e12,
+            "frac_of_one_cu": fpb / (kern_ms * 1e-3) / cu_peak,
+            "parity_ok": bool(ok[0]), "max_abs_dg": err}
+        plan.close()
+    best = min(res["by_waves"], key=lambda k: res["by_waves"][k]["call_latency_ms"])
+    res["best"] = best
+    res["call_latency_ms"] = res["by_waves"][best]["call_latency_ms"]
+    res["frac_of_one_cu"] = res["by_waves"][best]["frac_of_one_cu"]
+    res["one_cu_fp64_peak_tflops"] = cu_peak / 1e12
+    print(f"[bench] single block: {res['call_latency_ms']:.3f} ms per call ({best})", file=sys.stderr, flush=True)
+    return res
+
+
+def _host_info(workers: int):
+    """The host the CPU baseline ran on: model string, logical CPUs, the CPUs
+    this process may use, and the worker processes started (at most 16, the
+    host share of one GPU)."""
+    return {"cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "workers": workers}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -687,6 +781,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, copy MIB MiB once with a plain device copy, so "
                          "that a counter run can scale FETCH_SIZE / WRITE_SIZE by known bytes")
+    ap.add_argument("--no-single-block", action="store_true",
+                    help="skip the single-block (32x32, T=32, K=100) latency leg")
     ap.add_argument("--no-single-frame", action="store_true",
                     help="skip the one-frame latency launches (so a profiler's per-kernel "
                          "average covers only full-batch launches)")
@@ -870,6 +966,7 @@ def main():
         adj["graph_ms_per_step"] = t_g / args.steps * 1e3
         del graph
 
+    single_block = None if args.no_single_block else run_single_block(args, dev)
     dct = None if args.no_dct else run_dct(d_areas, d_known, target, n, args, dev, dct_base)
     ofse = None if args.no_ofse else run_ofse(d_areas, d_known, target, n, args, dev, ofse_base)
     tuning = run_tuning(tune_data, args, dev) if tune_data is not None else None
@@ -912,11 +1009,21 @@ def main():
                          {"blocks": n1, "ms": t_frame * 1e3, "blocks_per_s": n1 / t_frame}),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                     "credited_flop_note": "achieved counts the algorithmic FLOP per block (19 per conjugate "
+                                           "class and iteration plus two FFTs); the kernel issues fewer (see "
+                                           "executed_*)",
+                     "executed_flop_per_block": executed_flops_per_block(T, K),
+                     "executed_achieved": executed_flops_per_block(T, K) * n / kern / 1e12,
+                     "executed_frac": executed_flops_per_block(T, K) * n / kern / FP64_VECTOR_PEAK,
+                     "counter_flop_per_launch": measured_counter_flop(n),
+                     "counter_achieved": (None if measured_counter_flop(n) is None
+                                          else measured_counter_flop(n) / kern / 1e12),
                      "traffic": measured_traffic(n) if kname.startswith("fofse_group") else None,
                      "traffic_unit": "bytes per launch (HBM, counters scaled by a copy of known size)",
                      "kernel": kname, "flop_per_block": fpb,
                      "avg_launch_ms": kern * 1e3, "avg_step_ms": float(np.mean(per_step)) * 1e3},
         "block_status_nonzero": int(np.count_nonzero(status)),
+        "single_block": single_block,
         "fwd_adjoint": adj,
         "dct_basis": dct,
         "full_compensation": ofse,

@@ -27,6 +27,7 @@ struct fofse_plan_s {
     int32_t* d_bidx = nullptr;      // [M*N] index in the B list, -1 off B
     int b_m0 = 0, b_n0 = 0, b_h = 0, b_w = 0;
     double2* d_twiddle = nullptr;
+    double2* d_htw = nullptr;       // [2T] exp(-j pi q / T)
     double* d_wtab = nullptr;       // rho_hat ** dist per sample, refreshed per call
     double* d_dwtab = nullptr;      // its derivative in rho_hat (adjoint only)
     // per-block gradients when the caller passes no d_grad_block
@@ -94,6 +95,7 @@ void free_plan(fofse_plan p) {
     if (p->d_bpix) (void)hipFree(p->d_bpix);
     if (p->d_bidx) (void)hipFree(p->d_bidx);
     if (p->d_twiddle) (void)hipFree(p->d_twiddle);
+    if (p->d_htw) (void)hipFree(p->d_htw);
     if (p->d_wtab) (void)hipFree(p->d_wtab);
     if (p->d_dwtab) (void)hipFree(p->d_dwtab);
     if (p->d_gblk) (void)hipFree(p->d_gblk);
@@ -222,6 +224,7 @@ fofse_status extrapolate_impl(fofse_plan p, int32_t n_blocks, const float* d_are
     k.b_m0 = p->b_m0; k.b_n0 = p->b_n0; k.b_h = p->b_h; k.b_w = p->b_w;
     k.rho_gamma = d_rho_gamma;
     k.twiddle = p->d_twiddle;
+    k.htw = p->d_htw;
     k.wtab = p->d_wtab;
     k.out = d_out;
     k.sel = d_sel;
@@ -341,10 +344,14 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     }
     std::vector<uint8_t> target(M * N);
     for (int i = 0; i < M * N; ++i) target[i] = g->target_mask[i] ? 1 : 0;
-    std::vector<double2> tw(T);
+    std::vector<double2> tw(T), htw(2 * T);
     for (int q = 0; q < T; ++q) {
         const double ang = 2.0 * M_PI * (double)q / (double)T;
         tw[q] = make_double2(std::cos(ang), -std::sin(ang));
+    }
+    for (int q = 0; q < 2 * T; ++q) {
+        const double ang = M_PI * (double)q / (double)T;
+        htw[q] = make_double2(std::cos(ang), -std::sin(ang));
     }
 
     DeviceGuard guard(device);
@@ -363,6 +370,7 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
         hipMalloc(&p->d_bpix, bpix.size() * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_bidx, (size_t)M * N * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_twiddle, T * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->d_htw, 2 * T * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->d_wtab, (size_t)M * N * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->d_dwtab, (size_t)M * N * sizeof(double)) != hipSuccess) {
         free_plan(p);
@@ -371,7 +379,8 @@ fofse_status fofse_create(const fofse_geometry* g, int32_t device, fofse_plan* o
     if (hipMemcpy(p->d_target, target.data(), M * N, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_bpix, bpix.data(), bpix.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_bidx, bidx.data(), (size_t)M * N * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_twiddle, tw.data(), T * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(p->d_twiddle, tw.data(), T * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_htw, htw.data(), 2 * T * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(p);
         return FOFSE_ERR_DEVICE;
     }

@@ -266,6 +266,44 @@ __device__ __forceinline__ void fft64_stage_b_to_window(double2* win, int tid) {
     }
 }
 
+// The same last stage for a point-symmetric w: the window of real pairs of
+// run_wave_sym.  Grid row k of W, column c, gives V(a, c) = Re(conj(P(a, c))
+// W[k][c]) for each unreduced row a = k or k - T in -Q .. 3Q + 1, written as
+// the first element of entry a + Q and the second of entry a + Q - 1 (only
+// column c is written, so the two halves stay apart as above).
+template <int NT>
+__device__ __forceinline__ void fft64_stage_b_to_pairs(double2* win, const double2* ht, int R0, int C0, int tid) {
+    constexpr int T = 64, Q = 16;
+    static_assert(NT == 256, "one stage-B task per thread and half");
+    double* wd = reinterpret_cast<double*>(win);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int pc = kColHalves[(half << 5) | (tid & 31)];
+        const int k1 = tid >> 5;
+        double2 x[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) x[n2] = win[(8 * k1 + n2) * T + pc];
+        dft8(x);
+        __syncthreads();
+        const int c = FftPlan<T>::perm(pc);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            const int k = k1 + 8 * k2;                 // natural grid row
+#pragma unroll
+            for (int wrap = 0; wrap < 2; ++wrap) {
+                const int a = wrap ? k - T : k;
+                if (a < -Q || a > 3 * Q + 1) continue;
+                const double2 P = ht[(a * R0 + c * C0) & (2 * T - 1)];
+                const double val = P.x * x[k2].x + P.y * x[k2].y;
+                const int i = a + Q;
+                if (i <= T) wd[2 * (i * T + c)] = val;
+                if (i >= 1) wd[2 * ((i - 1) * T + c) + 1] = val;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // persistent grouped kernel: kGroup blocks x kWavesG waves per workgroup
 // ---------------------------------------------------------------------------
@@ -290,8 +328,10 @@ template <int T>
 struct GroupShared {
     double2 win[(T + 1) * T];
     double2 tw[T];
+    double2 ht[2 * T];                     // exp(-j pi q / T), q < 2T
     Xchg<kWavesG> xchg[kGroup][2];
     int flags[kGroup];
+    int asym;                              // the item's w is not point-symmetric
 };
 
 // One work item (up to kGroup blocks of one mask class) as seen by wave WI of
@@ -317,6 +357,7 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     const int b_rep = blk[0];              // every block of the item has this mask
     __syncthreads();                       // previous item done with LDS
     if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    if (tid == 0) sh.asym = 0;
 
     // weights of this thread's samples (eqs. 4, 15): identical for the item
     double wreg[MAXPX];
@@ -375,14 +416,31 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
         }
     }
     __syncthreads();
+    if constexpr (!FULL) {
+        // is w symmetric about the area's centre?  (the weights of mirrored
+        // samples are computed from the same distance, so they compare equal)
+        bool asym = false;
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q) {
+            const int i = tid + q * NT;
+            if (i < MN) {
+                const int m = i / N, n = i - m * N;
+                asym = asym || win[(N - 1 - n) * T + (M - 1 - m)].x != wreg[q];
+            }
+        }
+        if (asym) sh.asym = 1;
+        __syncthreads();
+    }
     fft_stage_a<T, NT>(win, sh.tw, N, T, 1, tid);
     __syncthreads();
     fft_stage_b<T, NT>(win, N, T, 1, tid);
     __syncthreads();
     fft_stage_a<T, NT>(win, sh.tw, T, 1, T, tid);
     __syncthreads();
-    fft64_stage_b_to_window<NT>(win, tid);
-    const double W0 = win[16 * T].x;      // W[0, 0] sits in window row 16
+    const bool sym = !FULL && sh.asym == 0;
+    if (sym) fft64_stage_b_to_pairs<NT>(win, sh.ht, N - 1, M - 1, tid);
+    else     fft64_stage_b_to_window<NT>(win, tid);
+    const double W0 = win[16 * T].x;      // W[0, 0] (V(0, 0)) sits in window row 16
 
     // the K iterations: every wave runs them (and their barriers); waves of a
     // missing or flagged block compute on zeros and write nothing
@@ -392,8 +450,16 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     const bool live = present && flags == 0;
     const int bj = blk[jblk];
     const double gW0 = live ? gamma / W0 : 0.0;
-    if (kWavesG > 1 || live)
+    if constexpr (kWavesG == 1 && !FULL) {
+        if (live && sym) {
+            rotate_rows<T>(R, sh.ht, N - 1, M - 1, lane);
+            run_wave_sym<T>(R, win, sh.ht, p, bj, lane, gW0);
+        } else if (live) {
+            run_wave<T, kWavesG, WI, FULL>(R, win, sh.xchg[jblk], p, bj, lane, gW0, live);
+        }
+    } else if (kWavesG > 1 || live) {
         run_wave<T, kWavesG, WI, FULL>(R, win, sh.xchg[jblk], p, bj, lane, gW0, live);
+    }
     if (present) {
         if (!live) {          // empty record: the synthesised model is 0
             for (int it = tib; it < K; it += kWavesG * 64) {
@@ -419,6 +485,7 @@ __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(K
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && (FULL || param_ok(gamma));   // the full compensation has no gamma
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
+    for (int i = tid; i < 2 * T; i += NT) sh.ht[i] = p.htw[i];
 
     // items of this workgroup: a contiguous range
     const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];

@@ -27,6 +27,7 @@ struct KParams {
     double* wtab;            // [M*N] rho_hat ** dist(centre), filled by k_weights
     double* dwtab;           // [M*N] d/drho_hat of wtab, or null (not needed)
     const double2* twiddle;  // [T] exp(-j 2 pi q / T)
+    const double2* htw;      // [2T] exp(-j pi q / T) (centring phase of a symmetric w)
     float* out;              // [n][nB]
     int32_t* sel;            // [n][K] selection record (caller's or plan workspace)
     double* coef;            // [n][K][2] coefficient record

@@ -304,4 +304,174 @@ __device__ __forceinline__ void run_wave(RegSpec<WaveRows<T, NW, WI>::S>& R,
 }
 
 
+// ---------------------------------------------------------------------------
+// the iteration for a point-symmetric weighting function (one wavefront per
+// block)
+// ---------------------------------------------------------------------------
+//
+// When w is symmetric about the area's centre, w[R0 - r][C0 - c] = w[r][c] on
+// the grid (R0 = grid rows of the area - 1, C0 = grid columns - 1), its
+// transform is a real function times a linear phase:
+//   W[a][b] = P(a, b) V(a, b),  P(a, b) = exp(-j pi (a R0 + b C0) / T),
+//   V(a, b) = sum w[r][c] cos(2 pi (a (r - R0/2) + b (c - C0/2)) / T)   (real),
+// for integer a, b (not reduced mod T): V(-a, -b) = V(a, b), and a shift of a
+// or b by T multiplies V by (-1)^R0 or (-1)^C0.  With the residual spectrum
+// rotated, Rt = conj(P) R, the update of eq. 3 in the DFT domain becomes
+//   Rt[k] -= ct V(k - u) + conj(ct) V(k + u),   ct = c conj(P(u)) = gamma Rt[u] / W0,
+// a real table and two real multiply-adds per part, and |Rt| = |R| leaves the
+// selection (eq. 9) unchanged.  The window holds the real table as pairs:
+// entry i (row i, column b) = (V(i - Q, b), V(i - Q + 1, b)), rows -Q .. 3Q + 1,
+// so one 16-byte read serves two neighbouring register slots.  Slot pairs
+// (2p, 2p + 1) read W[k - u] directly from row k - u when k >= Q and mirrored
+// (V(u - k, v - l)) when k < Q; W[k + u] directly from row k + u when
+// k <= Q + 1 and mirrored (V(T - k - u, -l - v) times (-1)^R0) otherwise;
+// column wraps give per-lane signs folded into per-lane coefficients.  ht
+// holds exp(-j pi q / T) for q in [0, 2T).
+// Slot pairs whose window reads are in flight ahead of the pair being updated.
+constexpr int kSymPrefetch = 2;
+
+template <int T>
+__device__ __forceinline__ void run_wave_sym(RegSpec<WaveRows<T, 1, 0>::S>& R, const double2* win,
+                                             const double2* ht, const KParams& p, int b, int lane,
+                                             double gW0) {
+    using L = Layout<T, 1>;
+    constexpr int S = WaveRows<T, 1, 0>::S;      // T/2 + 1 slots, rows 0 .. T/2
+    constexpr int H = L::H;
+    constexpr int Q = L::Q;
+    static_assert(S == H + 1 && (Q & 1) == 0 && (H & 1) == 0, "one wavefront holds rows 0 .. T/2");
+    const int K = p.K;
+    const int R0 = p.N - 1, C0 = p.M - 1;        // transposed placement: grid rows = area columns
+    const bool odd_r = (R0 & 1) != 0, odd_c = (C0 & 1) != 0;
+    const bool lane_ok = lane < T;
+    const bool edge_ok = lane_ok && lane <= H;
+    const int l = lane;
+    int u = 0, v = 0;
+    double ca = 0.0, cb = 0.0;
+    // window pointers of a selection (u, v): pair entry rows (window row =
+    // grid row + Q); every base row lies in the window and every per-slot
+    // offset is a non-negative constant
+    const double2 *p1d, *p1m, *p2d, *p2m;
+    auto set_ptrs = [&](int uu, int vv) {
+        p1d = win + (2 * Q - uu) * T + ((l - vv) & (T - 1));      // + (k - Q) T,     k >= Q
+        p1m = win + (uu + 1) * T + ((vv - l) & (T - 1));          // + (Q - 2 - k) T, k < Q even
+        p2d = win + (uu + Q) * T + ((l + vv) & (T - 1));          // + k T,           k <= Q even
+        p2m = win + (T + Q - 1 - uu - H) * T + ((-l - vv) & (T - 1));   // + (H - k) T, k > Q + 1 even
+    };
+    auto rd1 = [&](int k) -> double2 { return k >= Q ? p1d[(k - Q) * T] : p1m[(Q - 2 - k) * T]; };
+    auto rd2 = [&](int k) -> double2 { return k <= Q + 1 ? p2d[k * T] : p2m[(H - k) * T]; };
+    constexpr int NP = (S + 1) / 2;              // slot pairs (the last holds slot T/2 alone)
+    constexpr int D = kSymPrefetch < NP ? kSymPrefetch : NP;
+    double2 x1[NP], x2[NP];                      // fully unrolled: registers of the pairs in flight
+    set_ptrs(0, 0);
+#pragma unroll
+    for (int q = 0; q < D; ++q) { x1[q] = rd1(2 * q); x2[q] = rd2(2 * q); }
+    for (int it = 0; it < K; ++it) {
+        // per-lane signs of the column wraps (and the row shift of the mirrored
+        // second read) of the selection being applied, folded into the coefficients
+        const bool n1d = odd_c && l < v;
+        const bool n1m = odd_c && l > v;
+        const bool n2d = odd_c && l + v >= T;
+        const bool n2m = odd_r != (odd_c && l + v > 0 && l + v <= T);
+        const double a1d = n1d ? ca : -ca, b1d = n1d ? cb : -cb;
+        const double a1m = n1m ? ca : -ca, b1m = n1m ? cb : -cb;
+        const double a2d = n2d ? ca : -ca, b2d = n2d ? -cb : cb;
+        const double a2m = n2m ? ca : -ca, b2m = n2m ? -cb : cb;
+        double best = 0.0;
+        // slot pairs; the first D pairs' reads were issued with the selection,
+        // pair q + D is read before pair q is used
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int k = 2 * q;
+            if (q + D < NP) { x1[q + D] = rd1(k + 2 * D); x2[q + D] = rd2(k + 2 * D); }
+            // V1, V2 of slot k and (when present) slot k + 1
+            const double v1k  = k >= Q ? x1[q].x : x1[q].y;
+            const double v1k1 = k >= Q ? x1[q].y : x1[q].x;
+            const double v2k  = k <= Q + 1 ? x2[q].x : x2[q].y;
+            const double v2k1 = k <= Q + 1 ? x2[q].y : x2[q].x;
+            const double A1 = k >= Q ? a1d : a1m, B1 = k >= Q ? b1d : b1m;
+            const double A2 = k <= Q + 1 ? a2d : a2m, B2 = k <= Q + 1 ? b2d : b2m;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int s = k + h;
+                if (s >= S) break;
+                const double V1 = h ? v1k1 : v1k, V2 = h ? v2k1 : v2k;
+                double re = R.gr(s), im = R.gi(s);
+                re = fma(A1, V1, re);
+                re = fma(A2, V2, re);
+                im = fma(B1, V1, im);
+                im = fma(B2, V2, im);
+                R.set(s, re, im);
+                const double m2 = sq_add(im, re * re);
+                uint32_t lo = (__double2loint(m2) & 0xFFFFFFC0u) | (uint32_t)(63 - s);
+                int hi = __double2hiint(m2);
+                if (s == 0 || s == H) { hi = edge_ok ? hi : 0; lo = edge_ok ? lo : 0u; }
+                else if (T < 64)      { hi = lane_ok ? hi : 0; lo = lane_ok ? lo : 0u; }
+                best = max_f64(best, __hiloint2double(hi, (int)lo));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // wavefront maximum, ties to the smallest class key (as run_wave)
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        uint64_t hits = __ballot(bhi == mhi);
+        int wl = __builtin_ctzll(hits);
+        uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)blo, wl);
+        hits &= hits - 1;
+        while (hits) {
+            const int ln = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const uint32_t l2 = (uint32_t)__builtin_amdgcn_readlane((int)blo, ln);
+            if ((l2 & 0xFFFFFFC0u) > (mlo & 0xFFFFFFC0u)) { mlo = l2; wl = ln; }
+        }
+        mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)mlo);
+        wl = __builtin_amdgcn_readfirstlane(wl);
+        int wslot = (int)(63 - (mlo & 63u));
+        wslot = __builtin_amdgcn_readfirstlane(wslot >= S ? S - 1 : wslot);
+        u = wslot > H ? H : wslot;
+        v = wl & (T - 1);
+        // the next iteration's first window reads and the phase P(u) go out now,
+        // ahead of the coefficient
+        const double2 P = ht[(u * R0 + v * C0) & (2 * T - 1)];
+        set_ptrs(u, v);
+#pragma unroll
+        for (int q = 0; q < D; ++q) { x1[q] = rd1(2 * q); x2[q] = rd2(2 * q); }
+        const double2 wv = R.fetch(wslot, wl);             // Rt[u]
+        // eqs. 5, 14 in the rotated frame: ct = gamma Rt[u] / W0, c = ct P(u);
+        // a self-conjugate class keeps Re c
+        const bool selfc = (u == 0 || u == H) && (v == 0 || v == H);
+        double ctr = wv.x * gW0, cti = wv.y * gW0;
+        double cre = ctr * P.x - cti * P.y;
+        double cim = ctr * P.y + cti * P.x;
+        if (selfc) {             // c real; ct = c conj(P(u))
+            cim = 0.0;
+            ctr = cre * P.x;
+            cti = -cre * P.y;
+        }
+        if (lane == 0) {
+            const size_t r = (size_t)b * K + it;
+            p.sel[r] = v * T + u;
+            p.coef[2 * r] = cre;
+            p.coef[2 * r + 1] = cim;
+        }
+        // a self-conjugate class is applied as two half terms
+        ca = selfc ? 0.5 * ctr : ctr;
+        cb = selfc ? 0.5 * cti : cti;
+    }
+}
+
+// Rt = conj(P) R on the slots of a wavefront holding rows 0 .. T/2 (lane =
+// grid column): the rotation into the frame of run_wave_sym.
+template <int T>
+__device__ __forceinline__ void rotate_rows(RegSpec<WaveRows<T, 1, 0>::S>& R, const double2* ht, int R0, int C0,
+                                           int lane) {
+    constexpr int S = WaveRows<T, 1, 0>::S;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double2 P = ht[(s * R0 + lane * C0) & (2 * T - 1)];
+        const double re = R.gr(s), im = R.gi(s);
+        // conj(P) (re + j im)
+        R.set(s, re * P.x + im * P.y, im * P.x - re * P.y);
+    }
+}
+
 }  // namespace fofse
