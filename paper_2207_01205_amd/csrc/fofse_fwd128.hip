@@ -56,7 +56,7 @@ struct Shared128 {
 // ``val(i)`` gives the value of area sample i = m * N + n (0 outside A).
 template <int NT, class F>
 __device__ __forceinline__ void row_half_spectrum(double2* spec, const double2* tw, int M, int N, int tid,
-                                                  F val) {
+                                                  F val, int* asym = nullptr) {
     constexpr int NW = NT / 64;
     constexpr int NJ = (ROWS128 + NW - 1) / NW;             // output rows per thread
     double* xs = reinterpret_cast<double*>(spec);         // staging xs[n * 64 + m]
@@ -67,6 +67,14 @@ __device__ __forceinline__ void row_half_spectrum(double2* spec, const double2* 
         xs[n * 64 + m] = val(i);
     }
     __syncthreads();
+    if (asym) {     // is x symmetric about the area's centre?  (reads only)
+        bool a = false;
+        for (int i = tid; i < M * N; i += NT) {
+            const int m = i / N, n = i - m * N;
+            a = a || xs[(N - 1 - n) * 64 + (M - 1 - m)] != xs[n * 64 + m];
+        }
+        if (a) *asym = 1;
+    }
     // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128), l = lg + NW j
     const int m = tid & 63, lg = tid >> 6;
     double2 acc[NJ];
@@ -261,6 +269,245 @@ __device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - r
     }
 }
 
+// ---------------------------------------------------------------------------
+// point-symmetric w: the real-table iteration (as run_wave_sym for T <= 64)
+// ---------------------------------------------------------------------------
+//
+// W[a][b] = P(a, b) V(a, b) with P(a, b) = exp(-j pi (a R0 + b C0) / 128) and V
+// real (R0, C0: grid rows and columns of the area - 1), so with Rt = conj(P) R
+// the update is Rt[k] -= ct V(k - u) + conj(ct) V(k + u), ct = gamma Rt[u] / W0.
+// The table V is stored for rows -32 .. 96 (window row = a + 32), 128 columns,
+// 8 bytes each (132 KB, in place of the complex row half).  A slot k >= 32 reads
+// V(k - u) directly and k < 32 through V(u - k, v - l); k <= 32 reads V(k + u)
+// directly and k > 32 through (-1)^R0 V(128 - k - u, -l - v): the form depends
+// on the slot's row only.  Column wraps give per-lane signs, folded into the
+// coefficients.  ht holds exp(-j pi q / 128), q < 256.
+constexpr int Q128 = 32;
+constexpr int VROWS128 = 3 * Q128 + 1 + Q128;     // rows -32 .. 96
+
+// The V window from the row half of W (natural column order) in spec, in place.
+// Round 1 computes rows a = -32 and a = 32 .. 96, which read W rows 32 .. 64
+// only, and writes a = 32 .. 96 (the bytes of W rows 32 .. 64); round 2 computes
+// a = -31 .. 31 from W rows 0 .. 31 and writes a = -32 .. 31.
+template <int NT>
+__device__ __forceinline__ void build_v128(double2* spec, const double2* ht, int R0, int C0, int tid) {
+    double* vw = reinterpret_cast<double*>(spec);
+    auto vval = [&](int a, int b) -> double {
+        // W[a mod 128][b] from the row half; rows beyond 64 or below 0 by W[-k] = conj W[k]
+        double2 w;
+        if (a >= 0 && a <= H128) w = spec[a * T128 + b];
+        else {
+            const int r = a < 0 ? -a : T128 - a;
+            const double2 x = spec[r * T128 + ((-b) & (T128 - 1))];
+            w = make_double2(x.x, -x.y);
+        }
+        const double2 P = ht[(a * R0 + b * C0) & (2 * T128 - 1)];
+        return P.x * w.x + P.y * w.y;             // Re(conj(P) W)
+    };
+    // round 1: a = 32 .. 96 (65 rows) and a = -32 (kept for round 2)
+    constexpr int N1 = 65 * T128, E1 = (N1 + NT - 1) / NT;
+    constexpr int E0 = (T128 + NT - 1) / NT;
+    double v1[E1], v0[E0];
+#pragma unroll
+    for (int e = 0; e < E1; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < N1) v1[e] = vval(32 + idx / T128, idx & (T128 - 1));
+    }
+#pragma unroll
+    for (int e = 0; e < E0; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < T128) v0[e] = vval(-Q128, idx);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E1; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < N1) vw[(32 + Q128) * T128 + idx] = v1[e];
+    }
+    __syncthreads();
+    // round 2: a = -31 .. 31 (63 rows), W rows 0 .. 31 are intact
+    constexpr int N2 = 63 * T128, E2 = (N2 + NT - 1) / NT;
+    double v2[E2];
+#pragma unroll
+    for (int e = 0; e < E2; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < N2) v2[e] = vval(-31 + idx / T128, idx & (T128 - 1));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E2; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < N2) vw[T128 + idx] = v2[e];          // rows a = -31 .. 31 start at window row 1
+    }
+#pragma unroll
+    for (int e = 0; e < E0; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < T128) vw[idx] = v0[e];                // window row 0 = a = -32
+    }
+    __syncthreads();
+}
+
+template <int NW, int WI>
+__device__ __forceinline__ void run_wave128_sym(RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
+                                                RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
+                                                const double* vw, const double2* ht, Xchg<NW>* xchg,
+                                                const KParams& p, int b, int lane, double gW0, bool live) {
+    constexpr int k0 = row_begin128<NW>(WI);
+    constexpr int S = row_begin128<NW>(WI + 1) - k0;
+    constexpr int Q = Q128;
+    const int K = p.K;
+    const int RR = p.N - 1, CC = p.M - 1;       // transposed placement
+    const bool odd_r = (RR & 1) != 0, odd_c = (CC & 1) != 0;
+    int u = 0, v = 0;
+    double ca = 0.0, cb = 0.0;
+    for (int it = 0; it < K; ++it) {
+        // per column half h (column c = lane + 64 h): column indices of the
+        // four read forms and the signs of their wraps
+        int col[2][4];
+        double A1d[2], B1d[2], A1m[2], B1m[2], A2d[2], B2d[2], A2m[2], B2m[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = lane + 64 * h;
+            col[h][0] = (c - v) & (T128 - 1);
+            col[h][1] = (v - c) & (T128 - 1);
+            col[h][2] = (c + v) & (T128 - 1);
+            col[h][3] = (-c - v) & (T128 - 1);
+            const bool n1d = odd_c && c < v;
+            const bool n1m = odd_c && c > v;
+            const bool n2d = odd_c && c + v >= T128;
+            const bool n2m = odd_r != (odd_c && c + v > 0 && c + v <= T128);
+            A1d[h] = n1d ? ca : -ca; B1d[h] = n1d ? cb : -cb;
+            A1m[h] = n1m ? ca : -ca; B1m[h] = n1m ? cb : -cb;
+            A2d[h] = n2d ? ca : -ca; B2d[h] = n2d ? -cb : cb;
+            A2m[h] = n2m ? ca : -ca; B2m[h] = n2m ? -cb : cb;
+        }
+        // window rows: W1 direct a = k - u, mirrored u - k; W2 direct k + u,
+        // mirrored 128 - k - u (window row = a + 32)
+        auto rd = [&](int k, int h, double& V1, double& V2) {
+            const int r1 = k >= Q ? k - u : u - k;
+            const int r2 = k <= Q ? k + u : T128 - k - u;
+            V1 = vw[(r1 + Q) * T128 + col[h][k >= Q ? 0 : 1]];
+            V2 = vw[(r2 + Q) * T128 + col[h][k <= Q ? 2 : 3]];
+        };
+        constexpr int CH = 2;
+        constexpr int NC = (S + CH - 1) / CH;
+        double xv[2][CH][2][2];                  // [buffer][slot][half][V1, V2]
+        auto load = [&](int q, int bf) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int s = q * CH + j;
+                if (s < S) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) rd(k0 + s, h, xv[bf][j][h][0], xv[bf][j][h][1]);
+                }
+            }
+        };
+        load(0, 0);
+        double best = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            if (q + 1 < NC) load(q + 1, (q + 1) & 1);
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int s = q * CH + j;
+                if (s >= S) break;
+                const int k = k0 + s;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double V1 = xv[q & 1][j][h][0], V2 = xv[q & 1][j][h][1];
+                    const double a1 = k >= Q ? A1d[h] : A1m[h], b1 = k >= Q ? B1d[h] : B1m[h];
+                    const double a2 = k <= Q ? A2d[h] : A2m[h], b2 = k <= Q ? B2d[h] : B2m[h];
+                    double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
+                    re = fma(a1, V1, re);
+                    re = fma(a2, V2, re);
+                    im = fma(b1, V1, im);
+                    im = fma(b2, V2, im);
+                    if (h) R1.set(s, re, im); else R0.set(s, re, im);
+                    // eq. 9 key: |R|^2, then column half (0 first), then smaller row
+                    const double m2 = sq_add(im, re * re);
+                    uint32_t lo = (__double2loint(m2) & 0xFFFFFF00u) | ((uint32_t)(1 - h) << 7) | (uint32_t)(127 - k);
+                    int hi = __double2hiint(m2);
+                    if (k == 0 || k == H128) {
+                        // rows 0 and 64 represent columns 0..64 only
+                        const bool ok = h == 0 || lane == 0;
+                        hi = ok ? hi : 0;
+                        lo = ok ? lo : 0u;
+                    }
+                    best = max_f64(best, __hiloint2double(hi, (int)lo));
+                }
+            }
+            if constexpr (NC > 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        // wavefront maximum and the exchange between the block's wavefronts (as
+        // run_wave128)
+        const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
+        const uint32_t mhi = wave_max_u32(bhi);
+        uint64_t hits = __ballot(bhi == mhi);
+        int wl = __builtin_ctzll(hits);
+        uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)blo, wl);
+        hits &= hits - 1;
+        while (hits) {
+            const int ln = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const uint32_t l2 = (uint32_t)__builtin_amdgcn_readlane((int)blo, ln);
+            if ((l2 & 0xFFFFFF80u) > (mlo & 0xFFFFFF80u)) { mlo = l2; wl = ln; }
+        }
+        mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)mlo);
+        wl = __builtin_amdgcn_readfirstlane(wl);
+        int wslot = (int)(127 - (mlo & 127u)) - k0;
+        wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
+        const bool whalf = ((mlo >> 7) & 1u) == 0u;
+        const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
+        Xchg<NW>& x = xchg[it & 1];
+        if (lane == 0) {
+            x.hi[WI] = mhi;
+            x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
+            const double vx = whalf ? wv1.x : wv0.x, vy = whalf ? wv1.y : wv0.y;
+            x.val[WI] = make_double2(vx, vy);
+        }
+        __syncthreads();
+        uint32_t chi[NW], clo[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+        int bw = 0;
+        uint32_t whi = chi[0], wlo = clo[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
+            bw = gt ? w : bw;
+            whi = gt ? chi[w] : whi;
+            wlo = gt ? clo[w] : wlo;
+        }
+        bw = __builtin_amdgcn_readfirstlane(bw);
+        wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
+        const double2 wv = x.val[bw];            // Rt[u]
+        u = 127 - (int)(wlo & 127u);
+        u = u > H128 ? H128 : u;
+        v = (63 - (int)((wlo >> 7) & 63u)) + (((wlo >> 13) & 1u) ? 0 : 64);
+        // eqs. 5, 14 in the rotated frame: ct = gamma Rt[u] / W0, c = ct P(u);
+        // a self-conjugate class keeps Re c
+        const bool selfc = (u == 0 || u == H128) && (v == 0 || v == H128);
+        const double2 P = ht[(u * RR + v * CC) & (2 * T128 - 1)];
+        double ctr = wv.x * gW0, cti = wv.y * gW0;
+        double cre = ctr * P.x - cti * P.y;
+        double cim = ctr * P.y + cti * P.x;
+        if (selfc) {
+            cim = 0.0;
+            ctr = cre * P.x;
+            cti = -cre * P.y;
+        }
+        if (live && WI == 0 && lane == 0) {
+            const size_t r = (size_t)b * K + it;
+            p.sel[r] = v * T128 + u;
+            p.coef[2 * r] = cre;
+            p.coef[2 * r + 1] = cim;
+        }
+        // a self-conjugate class is applied as two half terms
+        ca = selfc ? 0.5 * ctr : ctr;
+        cb = selfc ? 0.5 * cti : cti;
+    }
+}
+
 // One wavefront: take its rows of R from the LDS spectrum into registers,
 // join the W transform (all waves run the same barriers), then iterate.
 template <int NW, int WI, class FW>
@@ -354,11 +601,14 @@ constexpr int kBlocks128G = 2;
 constexpr int kWaves128G = 4;
 
 struct Shared128G {
-    double2 spec[ROWS128 * T128];
+    double2 spec[ROWS128 * T128];       // row half of a spectrum, or the V window of a symmetric w
     double2 tw[T128];
+    double2 ht[2 * T128];               // exp(-j pi q / 128), q < 256
     Xchg<kWaves128G> xchg[kBlocks128G][2];
     int flags[kBlocks128G];
+    int asym;                           // the item's w is not point-symmetric
 };
+static_assert(VROWS128 * T128 * sizeof(double) <= ROWS128 * T128 * sizeof(double2), "V window fits the row half");
 
 // One work item as seen by wave WI of block slot jb.  Every wave of the
 // workgroup runs the same sequence of barriers.
@@ -389,6 +639,7 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
     };
     __syncthreads();                              // previous item done with LDS
     if (tid < kBlocks128G) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+    if (tid == 0) sh.asym = 0;
 
     // eqs. 4, 7, 8: R of each block by its own transform; its waves take their rows
     RegSpec<S> R0, R1;
@@ -421,12 +672,30 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
         __syncthreads();                          // rows taken before the next transform
     }
     row_half_spectrum<NT>(sh.spec, sh.tw, M, N, tid,
-                          [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; });
+                          [&](int i) -> double { return support(i) ? p.wtab[i] : 0.0; }, &sh.asym);
     const double W0 = sh.spec[0].x;
     int flags = params_ok ? sh.flags[jb] : FOFSE_BLOCK_BAD_PARAM;   // out-of-range parameters: that flag alone
     if (flags == 0 && !(W0 > 0.0)) flags = FOFSE_BLOCK_NO_SUPPORT;
     const bool live = present && flags == 0;
-    run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg[jb], p, bj, lane, live ? gamma / W0 : 0.0, live);
+    const bool sym = sh.asym == 0;                // uniform over the workgroup
+    if (sym) {
+        build_v128<NT>(sh.spec, sh.ht, N - 1, M - 1, tid);
+        // Rt = conj(P) R on this wave's slots, both column halves
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double2 P = sh.ht[((k0 + s) * (N - 1) + (lane + 64 * h) * (M - 1)) & (2 * T128 - 1)];
+                const double re = h ? R1.gr(s) : R0.gr(s), im = h ? R1.gi(s) : R0.gi(s);
+                const double nr = re * P.x + im * P.y, ni = im * P.x - re * P.y;
+                if (h) R1.set(s, nr, ni); else R0.set(s, nr, ni);
+            }
+        }
+        run_wave128_sym<NW, WI>(R0, R1, reinterpret_cast<const double*>(sh.spec), sh.ht, sh.xchg[jb], p, bj,
+                                lane, live ? gamma / W0 : 0.0, live);
+    } else {
+        run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg[jb], p, bj, lane, live ? gamma / W0 : 0.0, live);
+    }
     if (present && !live) {                       // empty record: the synthesised model is 0
         for (int it = WI * 64 + lane; it < K; it += NW * 64) {
             p.sel[(size_t)bj * K + it] = 0;
@@ -449,6 +718,7 @@ __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && param_ok(gamma);
     for (int i = tid; i < T128; i += NT) sh.tw[i] = p.twiddle[i];
+    for (int i = tid; i < 2 * T128; i += NT) sh.ht[i] = p.htw[i];
     // items of this workgroup: a contiguous range
     const int n_items = g.direct ? (p.n_blocks + kBlocks128G - 1) / kBlocks128G : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;

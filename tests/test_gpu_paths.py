@@ -366,3 +366,39 @@ def test_gamma_one_dct(frame_img, T):
     out, sel, coef, st = run_gpu(plan, f, None, 1.0, 1.0, f"DCT near-orthogonal T={T}")
     check(oracle_dct(f, None, tgt, T, 1.0, 1.0, 60), tgt, out, sel, coef, st,
           f"DCT near-orthogonal T={T}", min_same=6)
+
+
+# ---------------------------------------------------------------------------
+# the grouped T = 64 kernel's real-table iteration for point-symmetric weights
+
+@pytest.mark.parametrize("T", [64, 128])
+@pytest.mark.parametrize("M,N", [(48, 48), (49, 47), (45, 50), (64, 64), (33, 64), (50, 36)])
+def test_symmetric_masks_grouped(frame_img, M, N, T):
+    """Support masks symmetric about the area's centre take the grouped
+    kernels' real-table iteration (its column and row wrap signs depend on the
+    parities of M and N); a mask with one sample removed takes the complex
+    path.  Both against the oracle, in one batch, with classes of several
+    blocks, for T = 64 and T = 128."""
+    rng = np.random.default_rng(M * 100 + N)
+    target = np.zeros((M, N), np.uint8)
+    bm, bn = (M - 16) // 2, (N - 16) // 2
+    target[bm:M - bm, bn:N - bn] = 1                      # centred: symmetric
+    assert np.array_equal(target, target[::-1, ::-1])
+    n = 24
+    y = rng.integers(0, frame_img.shape[0] - M, n)
+    x = rng.integers(0, frame_img.shape[1] - N, n)
+    areas = np.stack([frame_img[a:a + M, b:b + N] for a, b in zip(y, x)]).astype(np.float32)
+    sym = []
+    for _ in range(3):                                    # three symmetric mask classes
+        kn = (rng.uniform(size=(M, N)) < 0.9).astype(np.uint8)
+        sym.append(kn & kn[::-1, ::-1])
+    asym = sym[0].copy()
+    asym[2, 3] = 1 - asym[2, 3]                           # breaks the symmetry
+    assert not np.array_equal(asym * (1 - target), (asym * (1 - target))[::-1, ::-1])
+    masks = [sym[i % 3] for i in range(18)] + [asym] * 6
+    known = np.stack(masks).astype(np.uint8)
+    K = 150 if T == 64 else 120
+    plan = _plan(M, N, T, K, target, path="grouped")
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, f"symmetric masks {M}x{N} T={T} grouped")
+    ref = oracle_dft(areas, known, target, T, 0.8, 0.5, K)
+    check(ref, target, out, sel, coef, st, f"symmetric masks {M}x{N} T={T}", min_same=18)
