@@ -250,6 +250,20 @@ fofse_status fofse_extrapolate_batch_noalloc(fofse_plan plan, int32_t n_blocks,
 fofse_status fofse_set_waves(fofse_plan plan, int32_t waves);
 
 /*
+ * Resident workgroups per compute unit of the persistent grouped kernels
+ * (FOFSE_PATH_GROUPED, and AUTO when it picks the grouped path): the grid is
+ * that many workgroups per compute unit, each taking a contiguous range of the
+ * work items.  0 restores the default: 2 for fft_size 64 (forward and
+ * adjoint: two workgroups of four blocks fit a compute unit), 1 for fft_size
+ * 128.  Built: 1 or 2 for fft_size 64, 1 otherwise.  The DCT basis always runs
+ * one workgroup per compute unit.  Results do not depend on it (every block is
+ * computed the same way whatever its work item).
+ * Returns FOFSE_ERR_ARG for a NULL plan or a negative count,
+ * FOFSE_ERR_UNSUPPORTED for a count not built for the plan's FFT size.
+ */
+fofse_status fofse_set_occupancy(fofse_plan plan, int32_t wg_per_cu);
+
+/*
  * Profiling hook.  With timing enabled, every fofse_extrapolate_batch and
  * fofse_backward call records a pair of HIP events on its stream around its
  * main kernel (the iteration kernel, or the adjoint kernel; the weight,
@@ -328,6 +342,55 @@ fofse_status fofse_backward(fofse_plan plan, int32_t n_blocks,
 
 /* Release the plan and its device memory.  NULL is ignored. */
 void fofse_destroy(fofse_plan plan);
+
+/*
+ * Several geometries in one call (Section 2's problem for areas, missing areas
+ * and FFT sizes that differ from block to block).
+ *
+ * fofse_create_multi creates one plan per geometry (as fofse_create, with the
+ * same errors; at most FOFSE_MULTI_MAX_GEOMS geometries).
+ * fofse_multi_geometry_plan returns the plan of geometry g (owned by the
+ * multi plan; NULL for a bad index), on which fofse_set_path, fofse_set_waves,
+ * fofse_set_occupancy, fofse_set_basis, fofse_set_compensation and
+ * fofse_set_timing act as on any plan.
+ *
+ * fofse_extrapolate_multi runs n_blocks blocks of mixed geometries:
+ *   d_geom_id    device int32 [n_blocks]: geometry index of every block.
+ *   d_areas      device float, packed areas: block b's M_g x N_g samples,
+ *                row-major, start at element d_area_off[b].
+ *   d_area_off   device int64 [n_blocks]: element offset of every block (in
+ *                d_areas, d_known and d_out alike); areas may sit anywhere.
+ *   d_known      device uint8, the same layout as d_areas, or NULL (every
+ *                block's A is the complement of its B).
+ *   d_rho_gamma  device double [2], as in fofse_extrapolate_batch.
+ *   d_out        device float, the same layout as d_areas: g is written on the
+ *                samples of each block's B; every other element is left as it
+ *                was (d_out may be d_areas itself).
+ *   d_status     device int32 [n_blocks] or NULL: FOFSE_BLOCK_* bits.
+ * Every block gets exactly the result of fofse_extrapolate_batch on its
+ * geometry's plan.  The blocks are sorted by geometry on the device; the call
+ * then waits for the per-geometry counts (a few bytes copied to the host)
+ * before it enqueues the per-geometry work, so it cannot be captured into a
+ * graph (FOFSE_ERR_UNSUPPORTED under capture: use one plan per geometry
+ * there).  The selection records are plan-owned.  Staging for the gathered
+ * areas grows as in fofse_extrapolate_batch.
+ * Returns FOFSE_ERR_ARG for a NULL plan or required pointer, n_blocks < 0,
+ * or a geometry index out of range (found on the device; nothing is run
+ * then), FOFSE_ERR_NOMEM, FOFSE_ERR_DEVICE, or what a geometry's
+ * fofse_extrapolate_batch returns.  n_blocks == 0 is a no-op.
+ *
+ * fofse_destroy_multi releases the multi plan and its geometries' plans.
+ */
+#define FOFSE_MULTI_MAX_GEOMS 16
+typedef struct fofse_multi_plan_s* fofse_multi_plan;   /* opaque; owned by the library */
+fofse_status fofse_create_multi(const fofse_geometry* geometries, int32_t n_geoms, int32_t device,
+                                fofse_multi_plan* out);
+fofse_plan fofse_multi_geometry_plan(fofse_multi_plan plan, int32_t geom);
+fofse_status fofse_extrapolate_multi(fofse_multi_plan plan, int32_t n_blocks, const int32_t* d_geom_id,
+                                     const float* d_areas, const int64_t* d_area_off,
+                                     const uint8_t* d_known, const double* d_rho_gamma, float* d_out,
+                                     int32_t* d_status, void* stream);
+void fofse_destroy_multi(fofse_multi_plan plan);
 
 /* Static string for a status code (never NULL). */
 const char* fofse_status_str(fofse_status status);

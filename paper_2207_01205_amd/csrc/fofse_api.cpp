@@ -18,6 +18,7 @@ struct fofse_plan_s {
     int n_cu = 0;
     int path = FOFSE_PATH_AUTO;
     int waves = 0;                  // split path: wavefronts per block (0 = default)
+    int occupancy = 0;              // grouped path: workgroups per compute unit (0 = default)
     int basis = FOFSE_BASIS_DFT;
     int comp = FOFSE_COMP_CONSTANT;
     double* d_dct_cos = nullptr;    // DCT basis: cos(pi k (2m+1) / (2T)) at [m * T + k]
@@ -254,6 +255,7 @@ fofse_status extrapolate_impl(fofse_plan p, int32_t n_blocks, const float* d_are
         g.target = p->d_target;
         g.direct = d_known == nullptr;
         g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        g.wg_per_cu = p->occupancy;
         if (!g.direct) {
             const fofse_status wst = ensure_workspace(p, n_blocks, g, ws, st);
             if (wst != FOFSE_OK) return wst;
@@ -284,6 +286,7 @@ fofse_status extrapolate_impl(fofse_plan p, int32_t n_blocks, const float* d_are
         g.target = p->d_target;
         g.direct = d_known == nullptr;
         g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        g.wg_per_cu = p->occupancy;
         if (!g.direct) {
             const fofse_status wst = ensure_workspace(p, n_blocks, g, ws, st);
             if (wst != FOFSE_OK) return wst;
@@ -430,6 +433,13 @@ fofse_status fofse_set_compensation(fofse_plan p, int32_t mode) {
     return FOFSE_OK;
 }
 
+fofse_status fofse_set_occupancy(fofse_plan p, int32_t wg_per_cu) {
+    if (!p || wg_per_cu < 0) return FOFSE_ERR_ARG;
+    if (wg_per_cu > (p->T == 64 ? 2 : 1)) return FOFSE_ERR_UNSUPPORTED;
+    p->occupancy = wg_per_cu;
+    return FOFSE_OK;
+}
+
 fofse_status fofse_set_waves(fofse_plan p, int32_t waves) {
     if (!p || waves < 0) return FOFSE_ERR_ARG;
     if (!fofse::split_waves_built(p->T, waves)) return FOFSE_ERR_UNSUPPORTED;
@@ -543,6 +553,7 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
         g.target = p->d_target;
         g.direct = d_known == nullptr;
         g.vec16 = (p->M * p->N) % 16 == 0 && ((uintptr_t)d_known & 15) == 0;
+        g.wg_per_cu = p->occupancy;
         if (!g.direct) {
             const fofse_status wst = ensure_workspace(p, n_blocks, g, nullptr, st);
             if (wst != FOFSE_OK) return wst;

@@ -536,7 +536,7 @@ hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const Gr
         if (e != hipSuccess) return e;
     }
     const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
-    int grid = 2 * n_cu;
+    int grid = (g.wg_per_cu > 0 ? g.wg_per_cu : 2) * n_cu;     // two fit per compute unit
     if (grid > max_items) grid = max_items;
     ga.n_wg = grid;
     constexpr int NT = 64 * kGroup;

@@ -545,7 +545,7 @@ hipError_t launch_grouped(const KParams& p, const GroupArgs& g, int n_cu, hipStr
         if (eg != hipSuccess) return eg;
     }
     const int max_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : p.n_blocks;
-    int grid = 2 * n_cu;
+    int grid = (g.wg_per_cu > 0 ? g.wg_per_cu : 2) * n_cu;     // two fit per compute unit
     if (grid > max_items) grid = max_items;
     constexpr int NT = kGroup * kWavesG * 64;
     const int mn = p.M * p.N;

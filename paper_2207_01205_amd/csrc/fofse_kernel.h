@@ -78,6 +78,7 @@ struct GroupArgs {
     int gshift;                       // log2(gsize)
     int vec16;                        // MN % 16 == 0 and known 16-byte aligned: masks read 16 bytes at a time
     int n_wg;                         // workgroups of the persistent main kernel
+    int wg_per_cu;                    // resident workgroups per compute unit asked for (0: the kernel's default)
     int MN;                           // samples per area
     const uint8_t* known;             // [n][MN] or null
     const uint8_t* target;            // [MN]

@@ -38,10 +38,11 @@ FOFSE_BASIS_DCT = 1
 FOFSE_COMP_CONSTANT = 0
 FOFSE_COMP_FULL = 1
 
-EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves",
+EXPORTED = ("fofse_create", "fofse_target_count", "fofse_set_path", "fofse_set_waves", "fofse_set_occupancy",
             "fofse_set_basis", "fofse_set_compensation",
             "fofse_extrapolate_batch", "fofse_extrapolate_batch_noalloc",
             "fofse_backward", "fofse_set_timing", "fofse_kernel_times", "fofse_destroy",
+            "fofse_create_multi", "fofse_multi_geometry_plan", "fofse_extrapolate_multi", "fofse_destroy_multi",
             "fofse_status_str")
 
 BACKWARD_MAX_K = 2048
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     L.fofse_set_path.restype = ctypes.c_int
     L.fofse_set_waves.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_waves.restype = ctypes.c_int
+    L.fofse_set_occupancy.argtypes = [vp, ctypes.c_int32]
+    L.fofse_set_occupancy.restype = ctypes.c_int
     L.fofse_set_basis.argtypes = [vp, ctypes.c_int32]
     L.fofse_set_basis.restype = ctypes.c_int
     L.fofse_set_compensation.argtypes = [vp, ctypes.c_int32]
@@ -97,6 +100,15 @@ def load_library(path: str = LIB_PATH):
     L.fofse_kernel_times.restype = ctypes.c_int32
     L.fofse_destroy.argtypes = [vp]
     L.fofse_destroy.restype = None
+    L.fofse_create_multi.argtypes = [ctypes.POINTER(fofse_geometry), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(vp)]
+    L.fofse_create_multi.restype = ctypes.c_int
+    L.fofse_multi_geometry_plan.argtypes = [vp, ctypes.c_int32]
+    L.fofse_multi_geometry_plan.restype = vp
+    L.fofse_extrapolate_multi.argtypes = [vp, ctypes.c_int32] + [vp] * 8
+    L.fofse_extrapolate_multi.restype = ctypes.c_int
+    L.fofse_destroy_multi.argtypes = [vp]
+    L.fofse_destroy_multi.restype = None
     L.fofse_status_str.argtypes = [ctypes.c_int]
     L.fofse_status_str.restype = ctypes.c_char_p
     _lib = L
@@ -139,6 +151,12 @@ def fofse_set_waves(plan: int, waves: int) -> None:
     st = load_library().fofse_set_waves(plan, int(waves))
     if st != FOFSE_OK:
         raise FofseError(st, "fofse_set_waves")
+
+
+def fofse_set_occupancy(plan: int, wg_per_cu: int) -> None:
+    st = load_library().fofse_set_occupancy(plan, int(wg_per_cu))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_set_occupancy")
 
 
 def fofse_set_basis(plan: int, basis: int) -> None:
@@ -207,6 +225,44 @@ def fofse_destroy(plan: int) -> None:
     load_library().fofse_destroy(plan)
 
 
+MULTI_MAX_GEOMS = 16
+
+
+def fofse_create_multi(geometries, device: int = 0) -> int:
+    """geometries: sequence of (area_h, area_w, fft_size, iterations,
+    target_mask).  Returns the opaque multi-plan handle; raises FofseError."""
+    L = load_library()
+    masks = [np.ascontiguousarray(np.asarray(g[4], dtype=np.uint8).reshape(-1)) for g in geometries]
+    arr = (fofse_geometry * len(geometries))()
+    for i, (g, tm) in enumerate(zip(geometries, masks)):
+        if tm.size != g[0] * g[1]:
+            raise ValueError("target_mask must hold area_h * area_w bytes")
+        arr[i] = fofse_geometry(g[0], g[1], g[2], g[3], tm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    out = ctypes.c_void_p()
+    st = L.fofse_create_multi(arr, len(geometries), int(device), ctypes.byref(out))
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_create_multi")
+    return out.value
+
+
+def fofse_multi_geometry_plan(mplan: int, geom: int) -> int:
+    return load_library().fofse_multi_geometry_plan(mplan, int(geom)) or 0
+
+
+def fofse_extrapolate_multi(mplan: int, n_blocks: int, d_geom_id: int, d_areas: int, d_area_off: int,
+                            d_known: int, d_rho_gamma: int, d_out: int, d_status: int, stream: int) -> None:
+    """Raw call with device addresses (ints, 0 for NULL); raises FofseError."""
+    st = load_library().fofse_extrapolate_multi(mplan, int(n_blocks), d_geom_id or None, d_areas or None,
+                                                d_area_off or None, d_known or None, d_rho_gamma or None,
+                                                d_out or None, d_status or None, stream or None)
+    if st != FOFSE_OK:
+        raise FofseError(st, "fofse_extrapolate_multi")
+
+
+def fofse_destroy_multi(mplan: int) -> None:
+    load_library().fofse_destroy_multi(mplan)
+
+
 # --- torch convenience wrapper ---------------------------------------------
 
 class Plan:
@@ -226,6 +282,9 @@ class Plan:
 
     def set_waves(self, waves: int):
         fofse_set_waves(self.handle, waves)
+
+    def set_occupancy(self, wg_per_cu: int):
+        fofse_set_occupancy(self.handle, wg_per_cu)
 
     def set_basis(self, basis: int):
         """FOFSE_BASIS_DFT (default) or FOFSE_BASIS_DCT; with the DCT the

@@ -51,6 +51,10 @@ def test_null_arguments_rejected_without_gpu():
         assert L.fofse_create(ctypes.byref(g), 0, ctypes.byref(out)) == F.FOFSE_ERR_ARG
     assert L.fofse_extrapolate_batch(None, 1, None, None, None, None, None, None, None, None) == F.FOFSE_ERR_ARG
     assert L.fofse_extrapolate_batch_noalloc(None, 1, *([None] * 8)) == F.FOFSE_ERR_ARG
+    assert L.fofse_extrapolate_multi(None, 1, *([None] * 8)) == F.FOFSE_ERR_ARG
+    assert L.fofse_create_multi(None, 1, 0, ctypes.byref(out)) == F.FOFSE_ERR_ARG
+    assert L.fofse_multi_geometry_plan(None, 0) is None
+    L.fofse_destroy_multi(None)
     assert L.fofse_target_count(None) == 0
     assert L.fofse_set_path(None, 0) == F.FOFSE_ERR_ARG
     assert L.fofse_set_waves(None, 2) == F.FOFSE_ERR_ARG

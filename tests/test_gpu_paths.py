@@ -200,6 +200,50 @@ def test_split_wave_counts(frame_img, T, waves):
           f"split/{waves} T={T} per-block masks", min_same=n // 2)
 
 
+@pytest.mark.parametrize("T,occ", [(64, 1), (64, 2), (128, 1)])
+def test_grouped_occupancy(frame_img, T, occ):
+    """Every grouped-path grid the autotuner can pick (resident workgroups per
+    compute unit) gives the oracle's result, and the same bits as the default
+    grid; a count that is not built is refused."""
+    from paper_2207_01205_amd import fofse as F
+    block, support, K = _SPLIT_GEOM[T]
+    areas, target, _, _ = synth.mixed_blocks(frame_img, 500 + T + occ, block, support, 64)
+    side = areas.shape[1]
+    rng = np.random.default_rng(occ)
+    known = (rng.uniform(size=areas.shape) < 0.9).astype(np.uint8)
+    known[::2] = 1                                   # half of the blocks share the canonical mask
+    plan = _plan(side, side, T, K, target, path="grouped")
+    ref_run = run_gpu(plan, areas, known, 0.8, 0.5, f"grouped T={T} default grid")
+    plan.set_occupancy(occ)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, f"grouped T={T} {occ} workgroups per CU")
+    for x, y in zip(ref_run, (out, sel, coef, st)):
+        assert np.array_equal(x, y)
+    check(oracle_dft(areas, known, target, T, 0.8, 0.5, K), target, out, sel, coef, st,
+          f"grouped T={T} occupancy {occ}", min_same=32)
+    with pytest.raises(F.FofseError):
+        plan.set_occupancy(3 if T == 64 else 2)
+
+
+def test_autotune_cache(frame_img, tmp_path):
+    """The autotuner times every candidate once, stores its choice, and a
+    second call with the same key applies it without timing."""
+    from paper_2207_01205_amd.autotune import autotune, candidates
+    block, support, K = _SPLIT_GEOM[64]
+    areas, target, _, _ = synth.mixed_blocks(frame_img, 77, block, support, 256)
+    plan = _plan(48, 48, 64, 40, target)
+    a = _put(areas, np.float32)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=a.device)
+    cache = str(tmp_path / "autotune.json")
+    print("[gpu] autotune with a cache file", flush=True)
+    times, best = autotune(plan, a, rg, cache=cache)
+    assert set(times) == {c[0] for c in candidates(64)} and best in times
+    times2, best2 = autotune(plan, a, rg, cache=cache)
+    assert times2 == {} and best2 == best
+    out, sel, coef, st = run_gpu(plan, areas, None, 0.8, 0.5, f"autotuned ({best})")
+    check(oracle_dft(areas, None, target, 64, 0.8, 0.5, 40), target, out, sel, coef, st,
+          f"autotuned {best}", min_same=200)
+
+
 # ---------------------------------------------------------------------------
 # T = 64 areas larger than 48 x 48 (the larger-area kernel instantiations)
 
