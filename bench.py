@@ -723,33 +723,59 @@ def run_tuning(data, args, dev):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
-    theta = torch.logit(torch.tensor([RHO, GAMMA], dtype=torch.float64)).requires_grad_(True)
-    opt = torch.optim.Adam([theta], lr=args.tune_lr)
+    # Adam on theta = logit(rho_hat, gamma), made monotone: every step is one
+    # replay at the proposed parameters, which yields both the training loss
+    # there and its gradient; a proposal whose loss is higher than the current
+    # one is rejected and the step size halved.  The fixed-selection gradient is
+    # exact for the selection of the evaluated point but blind to selection
+    # changes, which dominate this loss, so a plain Adam step can go uphill.
     psnr0 = heldout_psnr([RHO, GAMMA])
-    losses, t_steps = [], 0.0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for it in range(args.tune):
-        params = torch.sigmoid(theta.detach())
+    t_steps = [0.0]
+
+    def evaluate(th):
+        params = torch.sigmoid(th)
         rg.copy_(params)
         e0.record()
         graph.replay()
         e1.record()
         torch.cuda.synchronize()
-        t_steps += e0.elapsed_time(e1) * 1e-3
-        losses.append(((out - truth) ** 2).mean().item())
-        g = grg.cpu()
-        theta.grad = g * params * (1.0 - params)
-        opt.step()
+        t_steps[0] += e0.elapsed_time(e1) * 1e-3
+        loss = ((out - truth) ** 2).mean().item()
+        return loss, grg.cpu() * params * (1.0 - params)
+
+    theta = torch.logit(torch.tensor([RHO, GAMMA], dtype=torch.float64))
+    m1 = torch.zeros(2, dtype=torch.float64)
+    m2 = torch.zeros(2, dtype=torch.float64)
+    b1, b2, lr = 0.9, 0.999, args.tune_lr
+    loss_cur, g_cur = evaluate(theta)
+    loss0, accepted, evals = loss_cur, 0, 1
+    for it in range(1, args.tune + 1):
+        m1 = b1 * m1 + (1 - b1) * g_cur
+        m2 = b2 * m2 + (1 - b2) * g_cur * g_cur
+        step = lr * (m1 / (1 - b1 ** it)) / (torch.sqrt(m2 / (1 - b2 ** it)) + 1e-8)
+        prop = theta - step
+        loss_p, g_p = evaluate(prop)
+        evals += 1
+        if loss_p <= loss_cur:
+            theta, loss_cur, g_cur = prop, loss_p, g_p
+            accepted += 1
+        else:
+            lr *= 0.5
+        params = torch.sigmoid(theta)
         print(f"[tune] step {it}: rho {params[0].item():.4f} gamma {params[1].item():.4f} "
-              f"loss {losses[-1]:.4f}", file=sys.stderr, flush=True)
-    final = [float(x) for x in torch.sigmoid(theta.detach())]
+              f"loss {loss_cur:.4f} ({'accepted' if loss_cur == loss_p else 'rejected'} {loss_p:.4f})",
+              file=sys.stderr, flush=True)
+    final = [float(x) for x in torch.sigmoid(theta)]
     psnr1 = heldout_psnr(final)
     del graph
     return {"frames": args.tune_frames, "frame": "3840x2160", "loss_fraction": 0.05,
-            "blocks_per_step": n, "steps": args.tune, "optimizer": f"Adam lr {args.tune_lr} on logit",
-            "blocks_per_s": n * args.tune / t_steps, "ms_per_step": t_steps / args.tune * 1e3,
+            "blocks_per_step": n, "steps": args.tune, "graph_replays": evals, "accepted_steps": accepted,
+            "optimizer": f"monotone Adam on logit(rho_hat, gamma), lr {args.tune_lr}, halved on a rejected step",
+            "lr_end": lr,
+            "blocks_per_s": n * evals / t_steps[0], "ms_per_step": t_steps[0] / evals * 1e3,
             "rho_gamma_start": [RHO, GAMMA], "rho_gamma_end": final,
-            "loss_start": losses[0], "loss_end": losses[-1],
+            "loss_start": loss0, "loss_end": loss_cur,
             "heldout_psnr_db_start": psnr0, "heldout_psnr_db_end": psnr1,
             "heldout": "8 further frames, PSNR over the lost-block pixels, output clipped to 0..255"}
 
@@ -770,10 +796,10 @@ def main():
                          "4x4 and 8x8 classes (needs --mixed > 0)")
     ap.add_argument("--mixed", type=int, default=25000, metavar="PER_CLASS",
                     help="blocks per size class of the mixed-size batch (0 = skip)")
-    ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
-                    help="also fit (rho_hat, gamma) by Adam for STEPS steps on 64 synthetic "
+    ap.add_argument("--tune", type=int, default=50, metavar="STEPS",
+                    help="fit (rho_hat, gamma) by monotone Adam for STEPS steps on 64 synthetic "
                          "3840x2160 frames with 5%% block loss, one captured graph per step "
-                         "(forward, MSE gradient, adjoint), and report held-out PSNR")
+                         "(forward, MSE gradient, adjoint), and report held-out PSNR (0 = skip)")
     ap.add_argument("--tune-frames", type=int, default=64)
     ap.add_argument("--jobs", type=int, default=16,
                     help="processes generating the synthetic inputs (1: in this process)")
