@@ -355,6 +355,10 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
         for (int j = 0; j < kGroup; ++j) blk[j] = g.item_blk[(size_t)item * kGroup + j];
     }
     const int b_rep = blk[0];              // every block of the item has this mask
+    // the thread index as an opaque per-item value: keeps the compiler from
+    // hoisting every per-thread sample address of the item's loops out of the
+    // item loop (they would be spilled for the whole kernel and reloaded per item)
+    asm volatile("" : "+v"(tid));
     __syncthreads();                       // previous item done with LDS
     if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     if (tid == 0) sh.asym = 0;
