@@ -648,6 +648,8 @@ def run_mixed(classes, refs, args, dev):
         del graph
     launch = min(t_launch, key=t_launch.get)
     t_batched = t_launch[launch]
+    adjoint = None if args.no_adjoint else run_mixed_adjoint(classes, plans, inputs, recs, rg, timed, steps,
+                                                             n_all, t_batched, dev)
     parity = []
     if refs is not None:
         for c, ref, o, (sel, _), st in zip(classes, refs, outs, recs, sts):
@@ -669,7 +671,49 @@ def run_mixed(classes, refs, args, dev):
                         "fp64_peak_frac": flops / t_batched / FP64_VECTOR_PEAK,
                         "organisation": tuned, "launch": launch,
                         "ms_per_launch_form": {k: round(v * 1e3, 3) for k, v in t_launch.items()}},
+            "fwd_adjoint": adjoint,
             "sample_parity": parity}
+
+
+def run_mixed_adjoint(classes, plans, inputs, recs, rg, timed, steps, n_all, t_fwd, dev):
+    """The adjoint of every class of the mixed batch for the record of the
+    batched forward (dL/dg a fixed pseudo-random field on B): the classes in
+    turn on one stream, each plan's default organisation.  Reports the adjoint
+    time per batch, the forward+adjoint rate and each class's adjoint kernel."""
+    import torch
+    from paper_2207_01205_amd import fofse as F
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    gos, gas = [], []
+    for i, (p_, (a, _)) in enumerate(zip(plans, inputs)):
+        n = int(a.shape[0])
+        g = np.random.default_rng(70 + i).normal(size=(n, p_.nB)).astype(np.float32)
+        gos.append(torch.from_numpy(g).to(dev))
+        gas.append(torch.empty_like(a))
+    grg = torch.zeros((len(plans), 2), dtype=torch.float64, device=dev)
+
+    def backward_all():
+        for i, (p_, (a, _), (sel, coef), go, ga) in enumerate(zip(plans, inputs, recs, gos, gas)):
+            F.fofse_backward(p_.handle, int(a.shape[0]), a.data_ptr(), 0, rg.data_ptr(), sel.data_ptr(),
+                             coef.data_ptr(), go.data_ptr(), ga.data_ptr(), grg[i].data_ptr(), 0, stream)
+
+    print("[bench] mixed batch: adjoint of every class", file=sys.stderr, flush=True)
+    t_bwd = timed(backward_all, steps)
+    per_class = {}
+    for p_ in plans:
+        F.fofse_set_timing(p_.handle, True)
+    for _ in range(steps):
+        backward_all()
+    torch.cuda.synchronize()
+    for c, p_, (a, _) in zip(classes, plans, inputs):
+        n = int(a.shape[0])
+        ms = float(np.mean(F.fofse_kernel_times(p_.handle, steps)))
+        F.fofse_set_timing(p_.handle, False)
+        fl = n * adjoint_flops_per_block(c["T"], c["K"], p_.nB)
+        per_class[f"{c['block']}x{c['block']}/T{c['T']}"] = {
+            "kernel_ms": round(ms, 4), "fp64_peak_frac": round(fl / (ms * 1e-3) / FP64_VECTOR_PEAK, 4)}
+    ok = bool(torch.isfinite(grg).all().item()) and all(bool(torch.isfinite(g).all().item()) for g in gas)
+    return {"adjoint_ms_per_batch": t_bwd * 1e3, "ms_per_batch": (t_fwd + t_bwd) * 1e3,
+            "blocks_per_s": n_all / (t_fwd + t_bwd), "adjoint_per_class": per_class, "finite": ok}
 
 
 def run_tuning(data, args, dev):

@@ -316,7 +316,8 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  * The plan's path (fofse_set_path) applies as in the forward: the grouped
  * adjoint (T = 64 and K <= 256) shares W and its rho_hat derivative between
  * the blocks of one support mask and runs one wavefront per block; otherwise
- * one workgroup per block.  Both give the same gradients up to the order of
+ * one workgroup per block.  For fft_size 128 (K <= 512) the workgroup keeps
+ * the Hermitian half of W, then of D = DFT(dw/drho_hat), in LDS.  Both give the same gradients up to the order of
  * FP64 rounding, and each is deterministic: the same inputs give the same bits,
  * whatever other blocks share the batch.
  *
@@ -326,7 +327,7 @@ int32_t fofse_kernel_times(fofse_plan plan, float* ms_out, int32_t max);
  *
  * Returns FOFSE_ERR_ARG for a NULL plan or a NULL required pointer (d_areas,
  * d_rho_gamma, d_sel, d_coef, d_grad_out) or n_blocks < 0,
- * FOFSE_ERR_UNSUPPORTED when K exceeds 2048, T exceeds 64, the plan's basis is
+ * FOFSE_ERR_UNSUPPORTED when K exceeds 2048 (512 for fft_size 128), the plan's basis is
  * the DCT (FOFSE_BASIS_DCT has no adjoint) or its compensation is
  * FOFSE_COMP_FULL, or when a plan-owned buffer would have to grow under
  * stream capture, FOFSE_ERR_NOMEM if a plan-owned buffer cannot be

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfofse.so")
-SOURCES = ["fofse_fwd.hip", "fofse_fwd128.hip", "fofse_group.hip", "fofse_bwd.hip", "fofse_bwd_group.hip",
+SOURCES = ["fofse_fwd.hip", "fofse_fwd128.hip", "fofse_group.hip", "fofse_bwd.hip", "fofse_bwd128.hip", "fofse_bwd_group.hip",
            "synth_mfma.hip", "fofse_dct.hip", "fofse_noalloc.hip", "fofse_multi.hip", "fofse_api.cpp"]
 ARCH = "gfx950"
 

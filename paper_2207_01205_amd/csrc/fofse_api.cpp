@@ -498,7 +498,8 @@ fofse_status fofse_backward(fofse_plan p, int32_t n_blocks, const float* d_areas
     if (!p || n_blocks < 0) return FOFSE_ERR_ARG;
     if (n_blocks == 0) return FOFSE_OK;
     if (!d_areas || !d_rho_gamma || !d_sel || !d_coef || !d_grad_out) return FOFSE_ERR_ARG;
-    if (p->K > fofse::kBackwardMaxK || p->T > 64 || p->basis != FOFSE_BASIS_DFT || p->comp != FOFSE_COMP_CONSTANT)
+    if (p->K > (p->T == 128 ? fofse::kBackwardMaxK128 : fofse::kBackwardMaxK) || p->basis != FOFSE_BASIS_DFT ||
+        p->comp != FOFSE_COMP_CONSTANT)
         return FOFSE_ERR_UNSUPPORTED;
     DeviceGuard guard(p->device);
     if (!guard.ok) return FOFSE_ERR_DEVICE;

@@ -492,11 +492,14 @@ static hipError_t launch_bwd(const BParams& p, hipStream_t stream) {
 
 hipError_t launch_backward(const KParams& wp, const BParams& p, double* d_sum, hipStream_t stream,
                            const Timing& tm) {
-    if ((p.T != 64 && p.T != 32 && p.T != 16) || p.K > kBackwardMaxK) return hipErrorInvalidValue;
+    const bool t128 = p.T == 128;
+    if ((p.T != 64 && p.T != 32 && p.T != 16 && !t128) || p.K > (t128 ? kBackwardMaxK128 : kBackwardMaxK))
+        return hipErrorInvalidValue;
     hipError_t e = launch_weights(wp, stream);
     if (e != hipSuccess) return e;
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
-    if (p.T == 64) e = p.K <= 256 ? launch_bwd<64, 256>(p, stream) : launch_bwd<64, kBackwardMaxK>(p, stream);
+    if (t128) e = launch_bwd128(p, stream);
+    else if (p.T == 64) e = p.K <= 256 ? launch_bwd<64, 256>(p, stream) : launch_bwd<64, kBackwardMaxK>(p, stream);
     else if (p.T == 32) e = p.K <= 256 ? launch_bwd<32, 256>(p, stream) : launch_bwd<32, kBackwardMaxK>(p, stream);
     else e = p.K <= 256 ? launch_bwd<16, 256>(p, stream) : launch_bwd<16, kBackwardMaxK>(p, stream);
     if (e != hipSuccess) return e;

@@ -61,8 +61,9 @@ struct BParams {
     int b_m0, b_n0, b_h, b_w; // bounding box of B
 };
 
-// Largest K the adjoint kernel holds in LDS.
+// Largest K the adjoint kernel holds in LDS (FFT sizes 16-64, and 128).
 constexpr int kBackwardMaxK = 2048;
+constexpr int kBackwardMaxK128 = 512;
 
 // Blocks per workgroup in the grouped path (they share one W).
 constexpr int kGroup = 4;
@@ -145,5 +146,6 @@ hipError_t launch_grouping(const GroupArgs& g, int n, hipStream_t stream);
 hipError_t launch_backward_grouped(const KParams& wp, const BParams& p, const GroupArgs& g, int n_cu,
                                    double* d_sum, hipStream_t stream, const Timing& tm);
 hipError_t launch_bwd_sum(const BParams& p, double* d_sum, hipStream_t stream);
+hipError_t launch_bwd128(const BParams& p, hipStream_t stream);
 
 }  // namespace fofse
