@@ -37,21 +37,60 @@ constexpr int HL = T / 2 + 1;          // columns of the half plane, l in [0, 64
 constexpr int PS = 2 * HL;             // stride of a pair of rows
 constexpr int NT = 512;                // threads per workgroup
 constexpr int KM = kBackwardMaxK128;   // largest K held in LDS
+static_assert(KM <= NT, "one thread per iteration in the last scatter");
 constexpr int NSPLIT = (T / 2 * HL + NT - 1) / NT;
 
 using KY = Key<T>;
 using FP = FftPlan<T>;
 
 // X[k][l] of a Hermitian spectrum stored on the half plane after the column
-// transform: X[k][l] at H[perm(k) * 65 + l] for l <= 64, conj X[-k][-l] otherwise.
-__device__ __forceinline__ double2 half_at(const double2* H, int k, int l) {
+// transform: X[k][l] at H[perm(k) * 65 + l] for l <= 64, conj X[-k][-l]
+// otherwise.  half_idx gives the entry and whether it is to be conjugated.
+__device__ __forceinline__ int half_idx(int k, int l, bool& conj) {
     k &= T - 1;
     l &= T - 1;
     const bool up = l <= T / 2;
+    conj = !up;
     const int kk = up ? k : (T - k) & (T - 1);
     const int ll = up ? l : T - l;
-    const double2 v = H[FP::perm(kk) * HL + ll];
-    return make_double2(v.x, up ? v.y : -v.y);
+    return FP::perm(kk) * HL + ll;
+}
+__device__ __forceinline__ double2 conj_if(double2 v, bool c) { return make_double2(v.x, c ? -v.y : v.y); }
+__device__ __forceinline__ double2 half_at(const double2* H, int k, int l) {
+    bool c;
+    const int i = half_idx(k, l, c);
+    return conj_if(H[i], c);
+}
+
+// Sum of v over aligned groups of G adjacent lanes (G = 1, 2, 4, 8 or 16,
+// uniform) by DPP exchanges within rows of 16; every lane of a group gets the
+// same bits (each step adds a value and its partner's in either order).
+__device__ __forceinline__ double group_sum(double v, int G) {
+    if (G >= 2) v += dpp_f64<0xB1, 0xF>(v);      // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_f64<0x4E, 0xF>(v);      // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_f64<0x141, 0xF>(v);     // row_half_mirror
+    if (G >= 16) v += dpp_f64<0x140, 0xF>(v);    // row_mirror
+    return v;
+}
+
+// Update of the adjoint cbar_i of a class u_i by a later class u_n with
+// finished adjoint cbar_n (sbar_n = g cbar_n, g = gamma / W0):
+//   cbar_i -= sbar_n conj(Wd) + pr_i conj(sbar_n) Ws,  Wd = W[u_n - u_i], Ws = W[u_n + u_i],
+// pr_i = 1 for a conjugate-pair class u_i, 0 for a self-conjugate one.  In
+// real arithmetic, with (cr, ci) = cbar_n:
+//   Re cbar_i -= cr a + ci b,  Im cbar_i -= ci c + cr d,
+//   a = g (Re Wd + pr_i Re Ws), b = g (Im Wd + pr_i Im Ws),
+//   c = g (Re Wd - pr_i Re Ws), d = g (pr_i Im Ws - Im Wd).
+struct Upd {
+    double a, b, c, d;
+};
+__device__ __forceinline__ Upd upd_coef(double2 wd, double2 ws, bool pr, double g) {
+    const double sr = pr ? ws.x : 0.0, si = pr ? ws.y : 0.0;
+    return {g * (wd.x + sr), g * (wd.y + si), g * (wd.x - sr), g * (si - wd.y)};
+}
+__device__ __forceinline__ void upd_apply(double2& cb, const Upd& u, double cr, double ci) {
+    cb.x = fma(-cr, u.a, fma(-ci, u.b, cb.x));
+    cb.y = fma(-ci, u.c, fma(-cr, u.d, cb.y));
 }
 
 // x = tab (w or dw/drho) on A, zero elsewhere, written as complex lines of
@@ -70,20 +109,39 @@ __device__ __forceinline__ int load_row_pairs(double2* H, const BParams& p, cons
         for (int h = 0; h < 2; ++h) {
             const int m = 2 * pr + h;
             v[h] = 0.0;
-            if (m < M && n < N) {
+            if (m < M && n < N) {           // every load issued before the tests
                 const int i = m * N + n;
-                const bool a = p.target[i] == 0 && (!p.known || p.known[ab + i] != 0);
-                if (a) {
-                    bool nf = false;
-                    if (check_finite) nf = nonfinite_bits(sample_bits(p.areas, ab + i));
-                    bad |= nf;
-                    v[h] = nf ? 0.0 : tab[i];
-                }
+                const uint8_t tg = p.target[i];
+                const uint8_t kn = p.known ? p.known[ab + i] : (uint8_t)1;
+                const uint32_t fb = check_finite ? sample_bits(p.areas, ab + i) : 0u;
+                const double x = tab[i];
+                const bool a = tg == 0 && kn != 0;
+                const bool nf = a && nonfinite_bits(fb);
+                bad |= nf;
+                v[h] = a && !nf ? x : 0.0;
             }
         }
         H[pr * PS + n] = make_double2(v[0], v[1]);
     }
     return bad;
+}
+
+// dL/dg on B (zero elsewhere) as row pairs, like load_row_pairs.
+__device__ __forceinline__ void load_grad_pairs(double2* H, const BParams& p, int b, int tid) {
+    const int M = p.M, N = p.N;
+    const float* go = p.grad_out + (size_t)b * p.nB;
+#pragma unroll 4
+    for (int t = tid; t < T / 2 * T; t += NT) {
+        const int pr = t >> 7, n = t & (T - 1);
+        double v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = 2 * pr + h;
+            const int q = m < M && n < N ? p.bidx[m * N + n] : -1;
+            v[h] = q >= 0 ? (double)go[q] : 0.0;
+        }
+        H[pr * PS + n] = make_double2(v[0], v[1]);
+    }
 }
 
 // 128-point FFTs along the 65 columns of the half plane (rows r at r * 65),
@@ -170,13 +228,12 @@ __device__ void real_out_fft2_half(double2* H, const double2* tw, int tid) {
 }
 
 __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
-    constexpr int CH = 256;                 // samples of B staged per pass
     __shared__ double2 H[T / 2 * PS];       // half plane, 133,120 B
     __shared__ double2 tw[T];
-    __shared__ int keyL[KM];
+    __shared__ __align__(16) int keyL[KM];  // keys, -1 past K
     __shared__ double2 cL[KM];
     __shared__ double2 cbL[KM];
-    __shared__ int2 gm[CH];                 // (dL/dg as float bits, m << 16 | n)
+    __shared__ Upd cfL[16 * 16];            // pair coefficients of the panel being solved
     __shared__ double red[2][NT / 64];
     __shared__ int s_flags;
 
@@ -190,14 +247,30 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
 
     for (int i = tid; i < T; i += NT) tw[i] = p.twiddle[i];
     const size_t rb = (size_t)b * K;
-    for (int i = tid; i < K; i += NT) {
-        const int key = p.sel[rb + i] & (T * T - 1);   // k * T + l, read modulo the grid
+    for (int i = tid; i < KM; i += NT) {
+        const int key = i < K ? p.sel[rb + i] & (T * T - 1) : -1;   // k * T + l, read modulo the grid
         keyL[i] = key;
-        // a self-conjugate class has a real coefficient (the forward writes 0)
-        const bool pr = KY::pair(KY::k(key), KY::l(key));
-        cL[i] = make_double2(p.coef[2 * (rb + i)], pr ? p.coef[2 * (rb + i) + 1] : 0.0);
+        if (i < K) {
+            // a self-conjugate class has a real coefficient (the forward writes 0)
+            const bool pr = KY::pair(KY::k(key), KY::l(key));
+            cL[i] = make_double2(p.coef[2 * (rb + i)], pr ? p.coef[2 * (rb + i) + 1] : 0.0);
+        }
     }
     if (tid == 0) s_flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
+
+    // cbar0_nu = mult Gbar[u_nu], Gbar = DFT of dL/dg on B: one real 2-D FFT
+    // while the half plane is still free
+    load_grad_pairs(H, p, b, tid);
+    __syncthreads();
+    real_fft2_half(H, tw, tid);
+    for (int nu = tid; nu < K; nu += NT) {
+        const int key = keyL[nu];
+        const int k = KY::k(key), l = KY::l(key);
+        const double2 g = half_at(H, k, l);
+        cbL[nu] = KY::pair(k, l) ? make_double2(2.0 * g.x, 2.0 * g.y) : make_double2(g.x, 0.0);
+    }
+    __syncthreads();
+
     const size_t ab = (size_t)b * MN;
     const int bad = load_row_pairs(H, p, p.wtab, ab, true, tid);
     __syncthreads();
@@ -218,131 +291,73 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
     }
     const double gW = gamma / W0;
 
-    // cbar0_nu = mult Gbar[u_nu], Gbar[k] = sum_B gbar[x] exp(-j 2 pi <k, x> / T);
-    // the samples of B are staged through LDS (padded with zeros to a
-    // multiple of 8)
-    for (int nu0 = 0; nu0 < K; nu0 += NT) {
-        const int nu = nu0 + tid;
-        const int key = nu < K ? keyL[nu] : 0;
-        const int k = KY::k(key), l = KY::l(key);
-        double ar = 0.0, ai = 0.0;
-        for (int q0 = 0; q0 < nB; q0 += CH) {
-            const int cnt = min(CH, nB - q0);
-            const int cnt8 = (cnt + 7) & ~7;
-            __syncthreads();
-            for (int i = tid; i < cnt8; i += NT) {
-                int2 v = make_int2(0, 0);
-                if (i < cnt) {
-                    const int flat = p.bpix[q0 + i];
-                    const int m = flat / N, n = flat - m * N;
-                    v = make_int2(__float_as_int(p.grad_out[(size_t)b * nB + q0 + i]), (m << 16) | n);
-                }
-                gm[i] = v;
-            }
-            __syncthreads();
-            for (int i = 0; i < cnt8; i += 8) {
-                int2 v[8];
-                double2 t[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = gm[i + u];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) t[u] = tw[(k * (v[u].y >> 16) + l * (v[u].y & 0xFFFF)) & (T - 1)];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const double g = (double)__int_as_float(v[u].x);
-                    ar = fma(g, t[u].x, ar);
-                    ai = fma(g, t[u].y, ai);
-                }
-            }
-        }
-        if (nu < K)
-            cbL[nu] = KY::pair(k, l) ? make_double2(2.0 * ar, 2.0 * ai) : make_double2(ar, 0.0);
-    }
-    __syncthreads();
-
-    // Transposed recurrence in panels of P iterations, from the last panel.
-    // Step pn: wave 0 takes the contributions of panel pn + 1 (solved in the
-    // previous step) into panel pn and resolves panel pn serially; at the same
-    // time waves 1-7 apply panel pn + 1 to every iteration before panel pn.
+    // Transposed recurrence in panels of P iterations, from the last panel,
+    // two barriers per panel.  Step pn:
+    //  1. all threads, one pair each: the contributions of panel pn + 1
+    //     (finished in the previous step) into panel pn, summed over 16
+    //     adjacent lanes in a fixed order, and the update coefficients of the
+    //     pairs i < j within panel pn into cfL (j-major, so that lane i of
+    //     wave 0 reads them without bank conflicts);
+    //  2. wave 0 resolves panel pn serially (its lanes are the panel's
+    //     iterations; the finished adjoint of iteration j reaches the earlier
+    //     lanes by readlane) while waves 1-7 apply panel pn + 1 to every
+    //     iteration before panel pn.
     constexpr int P = 16;
     const int NPAN = (K + P - 1) / P;
-    int kprev = 0;                       // wave 0: classes and finished adjoints of panel pn + 1
-    double2 cprev = make_double2(0.0, 0.0);
     for (int pn = NPAN - 1; pn >= 0; --pn) {
         const int base = pn * P;
         const int cnt = min(P, K - base);
         const int pbase = (pn + 1) * P;
         const int pcnt = pn + 1 < NPAN ? min(P, K - pbase) : 0;
+        {
+            const int i = (tid >> 4) & (P - 1), x = tid & (P - 1);
+            const int keyi = keyL[base + min(i, cnt - 1)];
+            const int ku = KY::k(keyi), lu = KY::l(keyi);
+            const bool pr = KY::pair(ku, lu);
+            if (tid < P * P) {
+                // x: an iteration of panel pn + 1
+                double2 acc = make_double2(0.0, 0.0);
+                if (i < cnt && x < pcnt) {
+                    const int kn = keyL[pbase + x];
+                    const double2 cbn = cbL[pbase + x];
+                    const Upd c = upd_coef(half_at(H, KY::k(kn) - ku, KY::l(kn) - lu),
+                                           half_at(H, KY::k(kn) + ku, KY::l(kn) + lu), pr, gW);
+                    upd_apply(acc, c, cbn.x, cbn.y);
+                }
+                acc.x = group_sum(acc.x, P);
+                acc.y = group_sum(acc.y, P);
+                if (x == 0 && i < cnt && pcnt > 0) {
+                    const double2 o = cbL[base + i];
+                    cbL[base + i] = make_double2(o.x + acc.x, o.y + acc.y);
+                }
+            } else if (i < x && x < cnt) {
+                // x: a later iteration j of panel pn
+                const int kj = keyL[base + x];
+                cfL[x * P + i] = upd_coef(half_at(H, KY::k(kj) - ku, KY::l(kj) - lu),
+                                          half_at(H, KY::k(kj) + ku, KY::l(kj) + lu), pr, gW);
+            }
+        }
+        __syncthreads();
         if (wave == 0) {
             const bool valid = lane < cnt;
             const int key = valid ? keyL[base + lane] : 0;
-            const int ku = KY::k(key), lu = KY::l(key);
-            const bool pr = KY::pair(ku, lu);
+            const bool pr = KY::pair(KY::k(key), KY::l(key));
+            const uint64_t pmask = __ballot(pr);
             double2 cb = valid ? cbL[base + lane] : make_double2(0.0, 0.0);
-            if (valid) {
-                for (int u0 = 0; u0 < pcnt; u0 += 4) {
-                    double sr[4], si[4];
-                    double2 wd[4], ws[4];
+            // coefficients 0 where lane >= j or j >= cnt: those updates change nothing
+            Upd cf[P];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int u = min(u0 + q, pcnt - 1);
-                        const int kn = __builtin_amdgcn_readlane(kprev, u);
-                        const double h = u0 + q < pcnt ? gW : 0.0;
-                        sr[q] = h * readlane_f64(cprev.x, u);
-                        si[q] = h * readlane_f64(cprev.y, u);
-                        wd[q] = half_at(H, KY::k(kn) - ku, KY::l(kn) - lu);
-                        ws[q] = half_at(H, KY::k(kn) + ku, KY::l(kn) + lu);
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        cb.x -= sr[q] * wd[q].x + si[q] * wd[q].y;     // sbar conj(W[u_n - u_i])
-                        cb.y -= si[q] * wd[q].x - sr[q] * wd[q].y;
-                        if (pr) {
-                            cb.x -= sr[q] * ws[q].x + si[q] * ws[q].y; // conj(sbar) W[u_n + u_i]
-                            cb.y -= sr[q] * ws[q].y - si[q] * ws[q].x;
-                        }
-                    }
-                }
-            }
-            // serial sweep of panel pn: each lane first takes W at the sums and
-            // differences with every later class of the panel into registers;
-            // the finished adjoint of iteration j reaches the others by readlane
-            double wr[P], wi[P], vr[P], vi[P];
-            if (lane < P) {
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int jj = min(j, cnt - 1);
-                    const int kj = __builtin_amdgcn_readlane(ku, jj), lj = __builtin_amdgcn_readlane(lu, jj);
-                    const double2 d = half_at(H, kj - ku, lj - lu);
-                    const double2 s = half_at(H, kj + ku, lj + lu);
-                    wr[j] = d.x;
-                    wi[j] = d.y;
-                    vr[j] = s.x;
-                    vi[j] = s.y;
-                }
-            }
+            for (int j = 0; j < P; ++j) cf[j] = lane < j && j < cnt ? cfL[j * P + lane] : Upd{0.0, 0.0, 0.0, 0.0};
+            // lane j's adjoint is final once the later lanes have updated it;
+            // its imaginary part counts only for a pair class
 #pragma unroll
             for (int j = P - 1; j >= 0; --j) {
-                if (j < cnt) {
-                    const int keyj = __builtin_amdgcn_readlane(key, j);
-                    const bool pj = KY::pair(KY::k(keyj), KY::l(keyj));
-                    const double cr = readlane_f64(cb.x, j);
-                    const double ci = pj ? readlane_f64(cb.y, j) : 0.0;
-                    if (lane == j) cb = make_double2(cr, ci);  // final adjoint of c_j
-                    const double sr = gW * cr, si = gW * ci;   // sbar_j
-                    if (lane < j) {
-                        cb.x -= sr * wr[j] + si * wi[j];
-                        cb.y -= si * wr[j] - sr * wi[j];
-                        if (pr) {
-                            cb.x -= sr * vr[j] + si * vi[j];
-                            cb.y -= sr * vi[j] - si * vr[j];
-                        }
-                    }
-                }
+                const double cr = readlane_f64(cb.x, j);
+                const double ci = (pmask >> j) & 1 ? readlane_f64(cb.y, j) : 0.0;
+                upd_apply(cb, cf[j], cr, ci);
             }
+            if (!pr) cb.y = 0.0;
             if (valid) cbL[base + lane] = cb;
-            kprev = key;
-            cprev = cb;
         } else if (pcnt > 0 && base > 0) {
             // panel pn + 1 into the iterations mu < base; G adjacent lanes share
             // the panel's iterations of one mu and meet by butterfly shuffles
@@ -354,39 +369,36 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
                 const int key = keyL[mu];
                 const int ku = KY::k(key), lu = KY::l(key);
                 const bool pr = KY::pair(ku, lu);
-                double ar = 0.0, ai = 0.0;
+                double2 acc = make_double2(0.0, 0.0);
                 for (int q0 = 0; q0 < NQ; q0 += 4) {
-                    double sr[4], si[4];
-                    double2 wd[4], ws[4];
+                    double cr[4], ci[4];
+                    int id[8];
+                    bool cj[8];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int nu = pbase + g + (q0 + q) * G;
                         const int v = min(nu, pbase + pcnt - 1);
                         const int key2 = keyL[v];
                         const double2 cbn = cbL[v];
-                        const double h = (q0 + q < NQ && nu < pbase + pcnt) ? gW : 0.0;
-                        sr[q] = h * cbn.x;
-                        si[q] = h * cbn.y;
-                        wd[q] = half_at(H, KY::k(key2) - ku, KY::l(key2) - lu);
-                        ws[q] = half_at(H, KY::k(key2) + ku, KY::l(key2) + lu);
+                        const bool use = q0 + q < NQ && nu < pbase + pcnt;
+                        cr[q] = use ? cbn.x : 0.0;
+                        ci[q] = use ? cbn.y : 0.0;
+                        id[2 * q] = half_idx(KY::k(key2) - ku, KY::l(key2) - lu, cj[2 * q]);
+                        id[2 * q + 1] = half_idx(KY::k(key2) + ku, KY::l(key2) + lu, cj[2 * q + 1]);
                     }
+                    double2 w[8];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ar -= sr[q] * wd[q].x + si[q] * wd[q].y;
-                        ai -= si[q] * wd[q].x - sr[q] * wd[q].y;
-                        if (pr) {
-                            ar -= sr[q] * ws[q].x + si[q] * ws[q].y;
-                            ai -= sr[q] * ws[q].y - si[q] * ws[q].x;
-                        }
-                    }
+                    for (int q = 0; q < 8; ++q) w[q] = H[id[q]];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        upd_apply(acc, upd_coef(conj_if(w[2 * q], cj[2 * q]), conj_if(w[2 * q + 1], cj[2 * q + 1]), pr, gW),
+                                  cr[q], ci[q]);
                 }
-                for (int o = 1; o < G; o <<= 1) {
-                    ar += __shfl_xor(ar, o, 64);
-                    ai += __shfl_xor(ai, o, 64);
-                }
+                acc.x = group_sum(acc.x, G);
+                acc.y = group_sum(acc.y, G);
                 if (g == 0) {
                     const double2 o = cbL[mu];
-                    cbL[mu] = make_double2(o.x + ar, o.y + ai);
+                    cbL[mu] = make_double2(o.x + acc.x, o.y + acc.y);
                 }
             }
         }
@@ -401,32 +413,60 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
 
     // rho terms of the recurrence: -sum_{mu<nu} Re(sbar_nu conj(c_mu D[u_nu - u_mu])
     //                                + sbar_nu conj(conj(c_mu) D[u_nu + u_mu]))
+    // Row mu of the pairs (nu = mu + 1 .. K - 1) and row K - 2 - mu hold K pairs
+    // together, so the rows go in such couples (the middle row alone when K is
+    // even) and slot (couple c, position q) of the C x K slots is a pair or
+    // nothing; four slots per thread are in flight at a time.
     double racc = 0.0;
-    if (K > 0) {
-        const int dmu = NT / K, dnu = NT - dmu * K;
-        int mu = tid / K, nu = tid - mu * K;
-        while (mu < K) {
-            if (nu > mu) {
-                const int km = keyL[mu], kn = keyL[nu];
-                const int ku = KY::k(km), lu = KY::l(km);
-                const double2 c = cL[mu];
-                const double2 cbn = cbL[nu];
-                const double sr = gW * cbn.x, si = gW * cbn.y;
-                const double2 dd = half_at(H, KY::k(kn) - ku, KY::l(kn) - lu);
-                double qr = c.x * dd.x - c.y * dd.y, qi = c.x * dd.y + c.y * dd.x;
+    {
+        const int C = K / 2;
+        const int total = C * K;
+        const float rK = K > 0 ? 1.0f / (float)K : 0.0f;
+        for (int i0 = tid; i0 < total; i0 += 4 * NT) {
+            int mu[4], nu[4];
+            bool ok[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = i0 + q * NT;
+                int c = (int)((float)idx * rK);
+                c += (c + 1) * K <= idx ? 1 : 0;
+                c -= c * K > idx ? 1 : 0;
+                const int pos = idx - c * K;
+                const int len0 = K - 1 - c;            // pairs of row c
+                const int m2 = K - 2 - c;              // its partner row
+                ok[q] = idx < total && (pos < len0 || m2 != c);
+                mu[q] = pos < len0 ? c : m2;
+                nu[q] = pos < len0 ? c + 1 + pos : m2 + 1 + (pos - len0);
+                if (!ok[q]) mu[q] = nu[q] = 0;
+            }
+            int km[4], kn[4];
+            double2 c[4], cbn[4], dd[4], ds[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                km[q] = keyL[mu[q]];
+                kn[q] = keyL[nu[q]];
+                c[q] = cL[mu[q]];
+                cbn[q] = cbL[nu[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ku = KY::k(km[q]), lu = KY::l(km[q]);
+                dd[q] = half_at(H, KY::k(kn[q]) - ku, KY::l(kn[q]) - lu);
+                ds[q] = half_at(H, KY::k(kn[q]) + ku, KY::l(kn[q]) + lu);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double h = ok[q] ? gW : 0.0;
+                const double sr = h * cbn[q].x, si = h * cbn[q].y;   // sbar_nu
+                // -Re(sbar conj(c_mu D[u_nu - u_mu]))
+                double qr = c[q].x * dd[q].x - c[q].y * dd[q].y, qi = c[q].x * dd[q].y + c[q].y * dd[q].x;
                 racc -= sr * qr + si * qi;
-                if (KY::pair(ku, lu)) {
-                    const double2 ds = half_at(H, KY::k(kn) + ku, KY::l(kn) + lu);
-                    qr = c.x * ds.x + c.y * ds.y;
-                    qi = c.x * ds.y - c.y * ds.x;
+                if (KY::pair(KY::k(km[q]), KY::l(km[q]))) {
+                    // -Re(sbar conj(conj(c_mu) D[u_nu + u_mu]))
+                    qr = c[q].x * ds[q].x + c[q].y * ds[q].y;
+                    qi = c[q].x * ds[q].y - c[q].y * ds[q].x;
                     racc -= sr * qr + si * qi;
                 }
-            }
-            mu += dmu;
-            nu += dnu;
-            if (nu >= K) {
-                nu -= K;
-                ++mu;
             }
         }
     }
@@ -442,58 +482,115 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
     // (w f)bar = Re sum_k Rbar0[k] exp(+j 2 pi <k, x> / T) = F y_h with
     // y = conj(Rbar0) on the grid, Rbar0[k] = gamma / W0 * sum_{nu: u_nu = k} cbar_nu,
     // and y_h[k] = (y[k] + conj y[-k]) / 2 its Hermitian part, given on the
-    // half plane.  Every bin is summed in iteration order by the first
-    // iteration that reaches it (directly or through -k).
-    for (int i = tid; i < T * HL; i += NT) H[i] = make_double2(0.0, 0.0);
+    // half plane.  An iteration reaches the bin (k, l) when l <= 64 and the
+    // bin (-k, -l) when l = 0 or l >= 64 (once when the two coincide).  Each
+    // bin's first 8 bytes first hold the first iteration that reaches it and
+    // the number of iterations that do (LDS atomics: min and add, so the
+    // result does not depend on their order); a bin reached once takes that
+    // iteration's term, a bin reached several times is summed in iteration
+    // order by its first iteration, a bin reached by none is cleared.
+    int* Hi = reinterpret_cast<int*>(H);
+    for (int i = tid; i < T * HL; i += NT) reinterpret_cast<int4*>(H)[i] = make_int4(K, 0, 0, 0);
     __syncthreads();
-    for (int nu = tid; nu < K; nu += NT) {
+    int bin[2] = {-1, -1}, hkey[2] = {-2, -2}, nkey[2] = {-2, -2};
+    double2 own[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    const int nu = tid;                     // K <= NT: one iteration per thread
+    if (nu < K) {
         const int key = keyL[nu];
         const int k = KY::k(key), l = KY::l(key);
+        const int nk = (T - k) & (T - 1), nl = (T - l) & (T - 1);
+        const double2 cbn = cbL[nu];
+        if (l <= T / 2) {
+            bin[0] = k * HL + l;
+            hkey[0] = key;
+            nkey[0] = nk * T + nl;
+            // y / 2, and conj(y) / 2 as well for a bin that is its own negative
+            own[0] = key == nkey[0] ? make_double2(cbn.x, 0.0) : make_double2(0.5 * cbn.x, -0.5 * cbn.y);
+        }
+        if ((l == 0 || l >= T / 2) && !(nk == k && nl == l)) {
+            bin[1] = nk * HL + nl;
+            hkey[1] = nk * T + nl;
+            nkey[1] = key;
+            own[1] = make_double2(0.5 * cbn.x, 0.5 * cbn.y);       // conj(y) / 2
+        }
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            int hk = k, hl = l;
-            if (side == 0) {
-                if (l > T / 2) continue;
-            } else {
-                if (l != 0 && l < T / 2) continue;
-                hk = (T - k) & (T - 1);
-                hl = (T - l) & (T - 1);
-                if (hk == k && hl == l) continue;       // same bin as side 0
+        for (int sd = 0; sd < 2; ++sd) {
+            if (bin[sd] >= 0) {
+                atomicMin(&Hi[4 * bin[sd]], nu);
+                atomicAdd(&Hi[4 * bin[sd] + 1], 1);
             }
-            const int hkey = hk * T + hl;
-            const int nkey = ((T - hk) & (T - 1)) * T + ((T - hl) & (T - 1));
-            int first = K;
-            double sr = 0.0, si = 0.0;
-            for (int j = 0; j < K; ++j) {       // same trip count everywhere: broadcast reads
-                const int kj = keyL[j];
-                const double2 cbj = cbL[j];
-                const bool m1 = kj == hkey, m2 = kj == nkey;
-                first = (m1 || m2) && j < first ? j : first;
-                // y_j = conj(cbar_j) (times gamma / W0) directly, conj(y_j) through -k
-                sr += m1 ? cbj.x : 0.0;
-                si -= m1 ? cbj.y : 0.0;
-                sr += m2 ? cbj.x : 0.0;
-                si += m2 ? cbj.y : 0.0;
-            }
-            if (first == nu) H[hk * HL + hl] = make_double2(0.5 * gW * sr, 0.5 * gW * si);
         }
     }
+    __syncthreads();
+    int first[2] = {K, K}, count[2] = {0, 0};
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        if (bin[sd] >= 0) {
+            first[sd] = Hi[4 * bin[sd]];
+            count[sd] = Hi[4 * bin[sd] + 1];
+        }
+    }
+    constexpr int BPT = (T * HL + NT - 1) / NT;
+    bool unreached[BPT];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        const int i = tid + q * NT;
+        unreached[q] = i < T * HL && Hi[4 * i + 1] == 0;
+    }
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        if (first[sd] == nu && count[sd] > 1) {
+            // keys four at a time from the first iteration on, until every
+            // iteration of the bin is found (no earlier key matches)
+            double sr = 0.0, si = 0.0;
+            int left = count[sd];
+            const int4* k4 = reinterpret_cast<const int4*>(keyL);
+            for (int j4 = nu >> 2; left > 0 && j4 < KM / 4; ++j4) {
+                const int4 kk = k4[j4];
+                const int kv[4] = {kk.x, kk.y, kk.z, kk.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool m1 = kv[q] == hkey[sd], m2 = kv[q] == nkey[sd];
+                    if (m1 || m2) {
+                        const double2 cbj = cbL[4 * j4 + q];
+                        if (m1) {   // y_j = conj(cbar_j) directly
+                            sr += cbj.x;
+                            si -= cbj.y;
+                        }
+                        if (m2) {   // conj(y_j) through -k
+                            sr += cbj.x;
+                            si += cbj.y;
+                        }
+                        --left;
+                    }
+                }
+            }
+            own[sd] = make_double2(0.5 * sr, 0.5 * si);
+        }
+    }
+    __syncthreads();                        // every read of the counters done
+#pragma unroll
+    for (int q = 0; q < BPT; ++q)
+        if (unreached[q]) H[tid + q * NT] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+        if (first[sd] == nu) H[bin[sd]] = make_double2(gW * own[sd].x, gW * own[sd].y);
     __syncthreads();
     real_out_fft2_half(H, tw, tid);
 
     // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f)
     for (int i = tid; i < MN; i += NT) {
         const int m = i / N, n = i - m * N;
-        const bool a = p.target[i] == 0 && (!p.known || p.known[ab + i] != 0);
-        double gv = 0.0;
-        if (a) {
-            const int q = FP::perm(m);
-            const double2 v = H[(q >> 1) * PS + FP::perm(n)];
-            const double wfb = (q & 1) ? v.y : v.x;
-            gv = p.wtab[i] * wfb;
-            racc += p.dwtab[i] * (double)p.areas[ab + i] * wfb;
-        }
-        if (p.grad_areas) p.grad_areas[ab + i] = (float)gv;
+        const uint8_t tg = p.target[i];
+        const uint8_t kn = p.known ? p.known[ab + i] : (uint8_t)1;
+        const double w = p.wtab[i], dw = p.dwtab[i];
+        const float f = p.areas[ab + i];
+        const int q = FP::perm(m);
+        const double2 v = H[(q >> 1) * PS + FP::perm(n)];
+        const double wfb = (q & 1) ? v.y : v.x;
+        const bool a = tg == 0 && kn != 0;
+        if (a) racc += dw * (double)f * wfb;
+        if (p.grad_areas) p.grad_areas[ab + i] = a ? (float)(w * wfb) : 0.0f;
     }
 
     racc = wave_sum(racc);

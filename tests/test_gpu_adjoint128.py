@@ -159,3 +159,32 @@ def test_backward128_edge_cases():
     ga4, _, gb4 = gpu_backward(plan, areas[sub], known[sub], 0.8, 0.5, keys[sub], coef[sub], gbar_b[sub],
                                "T=128 sub-batch")
     assert np.array_equal(ga4, ga[sub]) and np.array_equal(gb4, gb[sub])
+
+
+def test_backward128_keys_on_both_half_planes(class128):
+    """Records that name a class by either of its two keys (u or -u), repeat
+    classes, and hit the columns l = 0 and l = 64 whose bins the half plane
+    holds twice, and the four self-conjugate classes; the coefficients are the
+    oracle's fixed-selection replay of those keys."""
+    areas, target = class128
+    areas = areas[:3]
+    T, K = 128, 160
+    f, kn = _support(areas, None, target)
+    ref = fofse(f, kn, T, 0.8, 0.5, K)
+    rng = np.random.default_rng(31)
+    keys = ref.keys.copy()
+    for i in range(keys.shape[0]):
+        u, v = keys[i] // T, keys[i] % T
+        flip = rng.random(K) < 0.5                       # the other key of the same class
+        keys[i] = np.where(flip, ((-u) % T) * T + ((-v) % T), keys[i])
+        special = [0 * T + 0, 64 * T + 0, 0 * T + 64, 64 * T + 64,      # self-conjugate
+                   5 * T + 0, 123 * T + 0, 7 * T + 64, 121 * T + 64]     # l = 0, 64 and their negatives
+        pos = rng.choice(K, size=len(special) + 6, replace=False)
+        keys[i, pos[:len(special)]] = special
+        keys[i, pos[len(special):]] = keys[i, rng.choice(K, size=6)]   # repeats
+    coef = np.stack([replay(f[i], kn[i], T, 0.8, 0.5, keys[i])[1] for i in range(keys.shape[0])])
+    gbar_b = rng.normal(size=(keys.shape[0], int(target.sum()))).astype(np.float32)
+    plan = _plan(64, 64, T, K, target)
+    ga, grg, gb = gpu_backward(plan, areas, None, 0.8, 0.5, keys, coef, gbar_b, "T=128 keys on both half planes")
+    fb, rb, gmb = oracle_adjoints(f, kn, target, T, 0.8, 0.5, keys, gbar_b)
+    check("T=128 keys on both half planes", ga, gb, grg, fb, rb, gmb)
