@@ -78,16 +78,18 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 //   cbar_i -= sbar_n conj(Wd) + pr_i conj(sbar_n) Ws,  Wd = W[u_n - u_i], Ws = W[u_n + u_i],
 // pr_i = 1 for a conjugate-pair class u_i, 0 for a self-conjugate one.  In
 // real arithmetic, with (cr, ci) = cbar_n:
-//   Re cbar_i -= cr a + ci b,  Im cbar_i -= ci c + cr d,
-//   a = g (Re Wd + pr_i Re Ws), b = g (Im Wd + pr_i Im Ws),
-//   c = g (Re Wd - pr_i Re Ws), d = g (pr_i Im Ws - Im Wd).
+//   Re cbar_i -= g (cr a + ci b),  Im cbar_i -= g (ci c + cr d),
+//   a = Re Wd + pr_i Re Ws, b = Im Wd + pr_i Im Ws,
+//   c = Re Wd - pr_i Re Ws, d = pr_i Im Ws - Im Wd.
+// upd_coef gives (a, b, c, d) for prf = pr_i as 0.0 or 1.0; the factor g is
+// applied to a sum of updates, or folded into the coefficients (upd_scale).
 struct Upd {
     double a, b, c, d;
 };
-__device__ __forceinline__ Upd upd_coef(double2 wd, double2 ws, bool pr, double g) {
-    const double sr = pr ? ws.x : 0.0, si = pr ? ws.y : 0.0;
-    return {g * (wd.x + sr), g * (wd.y + si), g * (wd.x - sr), g * (si - wd.y)};
+__device__ __forceinline__ Upd upd_coef(double2 wd, double2 ws, double prf) {
+    return {fma(prf, ws.x, wd.x), fma(prf, ws.y, wd.y), fma(-prf, ws.x, wd.x), fma(prf, ws.y, -wd.y)};
 }
+__device__ __forceinline__ Upd upd_scale(const Upd& u, double g) { return {g * u.a, g * u.b, g * u.c, g * u.d}; }
 __device__ __forceinline__ void upd_apply(double2& cb, const Upd& u, double cr, double ci) {
     cb.x = fma(-cr, u.a, fma(-ci, u.b, cb.x));
     cb.y = fma(-ci, u.c, fma(-cr, u.d, cb.y));
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
     for (int i = tid; i < KM; i += NT) {
         const int key = i < K ? p.sel[rb + i] & (T * T - 1) : -1;   // k * T + l, read modulo the grid
         keyL[i] = key;
+        cbL[i] = make_double2(0.0, 0.0);
         if (i < K) {
             // a self-conjugate class has a real coefficient (the forward writes 0)
             const bool pr = KY::pair(KY::k(key), KY::l(key));
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
             const int i = (tid >> 4) & (P - 1), x = tid & (P - 1);
             const int keyi = keyL[base + min(i, cnt - 1)];
             const int ku = KY::k(keyi), lu = KY::l(keyi);
-            const bool pr = KY::pair(ku, lu);
+            const double prf = KY::pair(ku, lu) ? 1.0 : 0.0;
             if (tid < P * P) {
                 // x: an iteration of panel pn + 1
                 double2 acc = make_double2(0.0, 0.0);
@@ -321,20 +324,20 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
                     const int kn = keyL[pbase + x];
                     const double2 cbn = cbL[pbase + x];
                     const Upd c = upd_coef(half_at(H, KY::k(kn) - ku, KY::l(kn) - lu),
-                                           half_at(H, KY::k(kn) + ku, KY::l(kn) + lu), pr, gW);
+                                           half_at(H, KY::k(kn) + ku, KY::l(kn) + lu), prf);
                     upd_apply(acc, c, cbn.x, cbn.y);
                 }
                 acc.x = group_sum(acc.x, P);
                 acc.y = group_sum(acc.y, P);
                 if (x == 0 && i < cnt && pcnt > 0) {
                     const double2 o = cbL[base + i];
-                    cbL[base + i] = make_double2(o.x + acc.x, o.y + acc.y);
+                    cbL[base + i] = make_double2(fma(gW, acc.x, o.x), fma(gW, acc.y, o.y));
                 }
             } else if (i < x && x < cnt) {
                 // x: a later iteration j of panel pn
                 const int kj = keyL[base + x];
-                cfL[x * P + i] = upd_coef(half_at(H, KY::k(kj) - ku, KY::l(kj) - lu),
-                                          half_at(H, KY::k(kj) + ku, KY::l(kj) + lu), pr, gW);
+                cfL[x * P + i] = upd_scale(upd_coef(half_at(H, KY::k(kj) - ku, KY::l(kj) - lu),
+                                                    half_at(H, KY::k(kj) + ku, KY::l(kj) + lu), prf), gW);
             }
         }
         __syncthreads();
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
                 const int mu = t / G, g = t - mu * G;
                 const int key = keyL[mu];
                 const int ku = KY::k(key), lu = KY::l(key);
-                const bool pr = KY::pair(ku, lu);
+                const double prf = KY::pair(ku, lu) ? 1.0 : 0.0;
                 double2 acc = make_double2(0.0, 0.0);
                 for (int q0 = 0; q0 < NQ; q0 += 4) {
                     double cr[4], ci[4];
@@ -391,14 +394,14 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
                     for (int q = 0; q < 8; ++q) w[q] = H[id[q]];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        upd_apply(acc, upd_coef(conj_if(w[2 * q], cj[2 * q]), conj_if(w[2 * q + 1], cj[2 * q + 1]), pr, gW),
+                        upd_apply(acc, upd_coef(conj_if(w[2 * q], cj[2 * q]), conj_if(w[2 * q + 1], cj[2 * q + 1]), prf),
                                   cr[q], ci[q]);
                 }
                 acc.x = group_sum(acc.x, G);
                 acc.y = group_sum(acc.y, G);
                 if (g == 0) {
                     const double2 o = cbL[mu];
-                    cbL[mu] = make_double2(o.x + acc.x, o.y + acc.y);
+                    cbL[mu] = make_double2(fma(gW, acc.x, o.x), fma(gW, acc.y, o.y));
                 }
             }
         }
@@ -483,14 +486,20 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
     // y = conj(Rbar0) on the grid, Rbar0[k] = gamma / W0 * sum_{nu: u_nu = k} cbar_nu,
     // and y_h[k] = (y[k] + conj y[-k]) / 2 its Hermitian part, given on the
     // half plane.  An iteration reaches the bin (k, l) when l <= 64 and the
-    // bin (-k, -l) when l = 0 or l >= 64 (once when the two coincide).  Each
-    // bin's first 8 bytes first hold the first iteration that reaches it and
-    // the number of iterations that do (LDS atomics: min and add, so the
-    // result does not depend on their order); a bin reached once takes that
-    // iteration's term, a bin reached several times is summed in iteration
-    // order by its first iteration, a bin reached by none is cleared.
+    // bin (-k, -l) when l = 0 or l >= 64 (once when the two coincide).
+    // Every bin's 16 bytes first hold four counters: the first iteration that
+    // reaches it (LDS atomic min), how many do (atomic add), and for a bin
+    // reached several times the start of its list of iterations in `seg` and
+    // that list's fill.  The lists are filled in any order; each member then
+    // finds its rank (the number of smaller iterations in its list), so that
+    // the first iteration sums the bin in iteration order.  Nothing here
+    // depends on the order of the atomics.  A bin reached by none is cleared.
     int* Hi = reinterpret_cast<int*>(H);
+    int* seg = reinterpret_cast<int*>(cfL);              // lists, then sorted lists
+    constexpr int SEG = KM * 2;                          // room for every (iteration, bin)
+    static_assert(2 * SEG * sizeof(int) <= sizeof(cfL), "lists fit in the panel coefficients");
     for (int i = tid; i < T * HL; i += NT) reinterpret_cast<int4*>(H)[i] = make_int4(K, 0, 0, 0);
+    if (tid == 0) s_flags = 0;                          // reused: list space taken so far
     __syncthreads();
     int bin[2] = {-1, -1}, hkey[2] = {-2, -2}, nkey[2] = {-2, -2};
     double2 own[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
@@ -528,6 +537,25 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
         if (bin[sd] >= 0) {
             first[sd] = Hi[4 * bin[sd]];
             count[sd] = Hi[4 * bin[sd] + 1];
+            if (first[sd] == nu && count[sd] > 1) Hi[4 * bin[sd] + 2] = atomicAdd(&s_flags, count[sd]);
+        }
+    }
+    __syncthreads();
+    int lbase[2] = {0, 0};
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        if (count[sd] > 1) {
+            lbase[sd] = Hi[4 * bin[sd] + 2];
+            seg[lbase[sd] + atomicAdd(&Hi[4 * bin[sd] + 3], 1)] = nu;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        if (count[sd] > 1) {
+            int rank = 0;
+            for (int q = 0; q < count[sd]; ++q) rank += seg[lbase[sd] + q] < nu ? 1 : 0;
+            seg[SEG + lbase[sd] + rank] = nu;
         }
     }
     constexpr int BPT = (T * HL + NT - 1) / NT;
@@ -537,38 +565,27 @@ __global__ __launch_bounds__(NT, 1) void fofse_bwd128_kernel(BParams p) {
         const int i = tid + q * NT;
         unreached[q] = i < T * HL && Hi[4 * i + 1] == 0;
     }
+    __syncthreads();
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
         if (first[sd] == nu && count[sd] > 1) {
-            // keys four at a time from the first iteration on, until every
-            // iteration of the bin is found (no earlier key matches)
             double sr = 0.0, si = 0.0;
-            int left = count[sd];
-            const int4* k4 = reinterpret_cast<const int4*>(keyL);
-            for (int j4 = nu >> 2; left > 0 && j4 < KM / 4; ++j4) {
-                const int4 kk = k4[j4];
-                const int kv[4] = {kk.x, kk.y, kk.z, kk.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const bool m1 = kv[q] == hkey[sd], m2 = kv[q] == nkey[sd];
-                    if (m1 || m2) {
-                        const double2 cbj = cbL[4 * j4 + q];
-                        if (m1) {   // y_j = conj(cbar_j) directly
-                            sr += cbj.x;
-                            si -= cbj.y;
-                        }
-                        if (m2) {   // conj(y_j) through -k
-                            sr += cbj.x;
-                            si += cbj.y;
-                        }
-                        --left;
-                    }
+            for (int q = 0; q < count[sd]; ++q) {
+                const int j = seg[SEG + lbase[sd] + q];
+                const int kj = keyL[j];
+                const double2 cbj = cbL[j];
+                if (kj == hkey[sd]) {   // y_j = conj(cbar_j) directly
+                    sr += cbj.x;
+                    si -= cbj.y;
+                }
+                if (kj == nkey[sd]) {   // conj(y_j) through -k
+                    sr += cbj.x;
+                    si += cbj.y;
                 }
             }
             own[sd] = make_double2(0.5 * sr, 0.5 * si);
         }
     }
-    __syncthreads();                        // every read of the counters done
 #pragma unroll
     for (int q = 0; q < BPT; ++q)
         if (unreached[q]) H[tid + q * NT] = make_double2(0.0, 0.0);
