@@ -39,6 +39,7 @@ constexpr int NT = 512;                // threads per workgroup
 constexpr int KM = kBackwardMaxK128;   // largest K held in LDS
 static_assert(KM <= NT, "one thread per iteration in the last scatter");
 constexpr int NSPLIT = (T / 2 * HL + NT - 1) / NT;
+constexpr int NSPLIT_LOW = (T / 4 * HL + NT - 1) / NT;
 
 using KY = Key<T>;
 using FP = FftPlan<T>;
@@ -95,35 +96,42 @@ __device__ __forceinline__ void upd_apply(double2& cb, const Upd& u, double cr, 
     cb.y = fma(-ci, u.c, fma(-cr, u.d, cb.y));
 }
 
-// x = tab (w or dw/drho) on A, zero elsewhere, written as complex lines of
-// row pairs H[p * 130 + n] = x[2p][n] + j x[2p + 1][n].  With check_finite the
-// known samples of f are tested and a non-finite one is reported in the
-// return value (its weight is taken as 0, as in the forward).
+// The area of a 128-point plan is at most 64 x 64, so in the grid of the
+// transforms rows and columns 64..127 are zero.  The loaders fill lines
+// p < 32 of the row pairs (rows 2p and 2p + 1 as H[p * 130 + n] = x[2p][n] +
+// j x[2p + 1][n], zero for n >= 64); lines 32..63 are not used.  Every load
+// goes out before the first test (out-of-area samples read index 0).
+constexpr int LINES = T / 4;                  // row pairs that can hold samples
+constexpr int LOADS = LINES * (T / 2) / NT;   // loaded entries per thread
+
+// x = tab (w or dw/drho) on A, zero elsewhere.  With check_finite the known
+// samples of f are tested and a non-finite one is reported in the return
+// value (its weight is taken as 0, as in the forward).
 __device__ __forceinline__ int load_row_pairs(double2* H, const BParams& p, const double* tab, size_t ab,
                                               bool check_finite, int tid) {
     const int M = p.M, N = p.N;
     int bad = 0;
-#pragma unroll 4
-    for (int t = tid; t < T / 2 * T; t += NT) {
-        const int pr = t >> 7, n = t & (T - 1);
+#pragma unroll
+    for (int s = 0; s < LOADS; ++s) {
+        const int t = tid + s * NT;
+        const int pr = t >> 6, n = t & (T / 2 - 1);
         double v[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int m = 2 * pr + h;
-            v[h] = 0.0;
-            if (m < M && n < N) {           // every load issued before the tests
-                const int i = m * N + n;
-                const uint8_t tg = p.target[i];
-                const uint8_t kn = p.known ? p.known[ab + i] : (uint8_t)1;
-                const uint32_t fb = check_finite ? sample_bits(p.areas, ab + i) : 0u;
-                const double x = tab[i];
-                const bool a = tg == 0 && kn != 0;
-                const bool nf = a && nonfinite_bits(fb);
-                bad |= nf;
-                v[h] = a && !nf ? x : 0.0;
-            }
+            const bool in = m < M && n < N;
+            const int i = in ? m * N + n : 0;
+            const uint8_t tg = p.target[i];
+            const uint8_t kn = p.known ? p.known[ab + i] : (uint8_t)1;
+            const uint32_t fb = check_finite ? sample_bits(p.areas, ab + i) : 0u;
+            const double x = tab[i];
+            const bool a = in && tg == 0 && kn != 0;
+            const bool nf = a && nonfinite_bits(fb);
+            bad |= nf;
+            v[h] = a && !nf ? x : 0.0;
         }
         H[pr * PS + n] = make_double2(v[0], v[1]);
+        H[pr * PS + T / 2 + n] = make_double2(0.0, 0.0);
     }
     return bad;
 }
@@ -132,17 +140,52 @@ __device__ __forceinline__ int load_row_pairs(double2* H, const BParams& p, cons
 __device__ __forceinline__ void load_grad_pairs(double2* H, const BParams& p, int b, int tid) {
     const int M = p.M, N = p.N;
     const float* go = p.grad_out + (size_t)b * p.nB;
-#pragma unroll 4
-    for (int t = tid; t < T / 2 * T; t += NT) {
-        const int pr = t >> 7, n = t & (T - 1);
-        double v[2];
+    int q[LOADS][2];
+#pragma unroll
+    for (int s = 0; s < LOADS; ++s) {
+        const int t = tid + s * NT;
+        const int pr = t >> 6, n = t & (T / 2 - 1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int m = 2 * pr + h;
-            const int q = m < M && n < N ? p.bidx[m * N + n] : -1;
-            v[h] = q >= 0 ? (double)go[q] : 0.0;
+            const bool in = m < M && n < N;
+            const int qq = p.bidx[in ? m * N + n : 0];
+            q[s][h] = in ? qq : -1;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < LOADS; ++s) {
+        const int t = tid + s * NT;
+        const int pr = t >> 6, n = t & (T / 2 - 1);
+        double v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float g = go[q[s][h] >= 0 ? q[s][h] : 0];
+            v[h] = q[s][h] >= 0 ? (double)g : 0.0;
         }
         H[pr * PS + n] = make_double2(v[0], v[1]);
+        H[pr * PS + T / 2 + n] = make_double2(0.0, 0.0);
+    }
+}
+
+// Stage A of the column FFTs when rows 64..127 of the input are zero: of the
+// samples 8 n1 + n2 only n1 < 8 are read (writes cover every row).
+__device__ __forceinline__ void column_stage_a_low(double2* H, const double2* tw, int tid) {
+    constexpr int R1 = FP::R1;
+    for (int task = tid; task < HL * 8; task += NT) {
+        const bool main = task < (T / 2) * 8;
+        const int line = main ? task & (T / 2 - 1) : T / 2;
+        const int n2 = main ? task >> 6 : task - (T / 2) * 8;
+        double2* base = H + line;
+        double2 x[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) x[n1] = n1 < R1 / 2 ? base[(8 * n1 + n2) * HL] : make_double2(0.0, 0.0);
+        dft<R1>(x);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const double2 v = k1 ? c_mul(x[k1], tw[(n2 * k1) & (T - 1)]) : x[k1];
+            base[(8 * k1 + n2) * HL] = v;
+        }
     }
 }
 
@@ -160,18 +203,18 @@ __device__ __forceinline__ void column_fft(double2* H, const double2* tw, int ti
 // Half spectrum of the real grid loaded by load_row_pairs: X[k][l], l <= 64,
 // at H[perm(k) * 65 + l].
 __device__ void real_fft2_half(double2* H, const double2* tw, int tid) {
-    fft_stage_a<T, NT>(H, tw, T / 2, PS, 1, tid);
+    fft_stage_a<T, NT>(H, tw, LINES, PS, 1, tid);
     __syncthreads();
-    fft_stage_b<T, NT>(H, T / 2, PS, 1, tid);
+    fft_stage_b<T, NT>(H, LINES, PS, 1, tid);
     __syncthreads();
     // the FFT Z of line p holds the spectra of its two real rows:
     // X_2p[l] = (Z[l] + conj Z[-l]) / 2, X_2p+1[l] = (Z[l] - conj Z[-l]) / (2j)
-    double2 a[NSPLIT], b[NSPLIT];
+    double2 a[NSPLIT_LOW], b[NSPLIT_LOW];
 #pragma unroll
-    for (int s = 0; s < NSPLIT; ++s) {
+    for (int s = 0; s < NSPLIT_LOW; ++s) {
         const int t = tid + s * NT;
         a[s] = b[s] = make_double2(0.0, 0.0);
-        if (t < T / 2 * HL) {
+        if (t < LINES * HL) {
             const int pr = t / HL, l = t - pr * HL;
             const double2 z = H[pr * PS + FP::perm(l)];
             const double2 zm = H[pr * PS + FP::perm((T - l) & (T - 1))];
@@ -181,16 +224,21 @@ __device__ void real_fft2_half(double2* H, const double2* tw, int tid) {
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < NSPLIT; ++s) {
+    for (int s = 0; s < NSPLIT_LOW; ++s) {
         const int t = tid + s * NT;
-        if (t < T / 2 * HL) {
+        if (t < LINES * HL) {
             const int pr = t / HL, l = t - pr * HL;
             H[pr * PS + l] = a[s];          // row 2p at (2p) * 65
             H[pr * PS + HL + l] = b[s];     // row 2p + 1 at (2p + 1) * 65
         }
     }
     __syncthreads();
-    column_fft(H, tw, tid);
+    // rows 64..127 are zero: stage A reads rows 0..63 only and writes all
+    column_stage_a_low(H, tw, tid);
+    __syncthreads();
+    fft_stage_b<T, NT>(H, T / 2, 1, HL, tid);
+    fft_stage_b<T, NT>(H + T / 2, 1, 1, HL, tid);
+    __syncthreads();
 }
 
 // y[m][n] = sum_{k,l} Y[k][l] exp(-j 2 pi (k m + l n) / T) for a Hermitian Y
