@@ -37,18 +37,22 @@ FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
 # HBM traffic of the main forward kernel per launch on the 16-frame batch,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
 # of ``bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame
-# --no-adjoint --mixed 0 --no-dct --no-ofse --copy-calibration 256 --jobs 1``.  In those runs a plain 256 MiB device copy read
-# FETCH_SIZE = 131,095 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is scaled
-# by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel sources it
-# was taken on (hash below); otherwise the bench reports null.
+# --no-single-block --no-adjoint --mixed 0 --no-dct --no-ofse --tune 0
+# --copy-calibration 256 --jobs 1``.  In those runs a plain 256 MiB device copy
+# read FETCH_SIZE = 131,093 KiB and WRITE_SIZE = 262,144 KiB, so FETCH_SIZE is
+# scaled by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel
+# sources it was taken on (hash below); otherwise the bench reports null.
 KERNEL_SOURCES = ("fofse_group.hip", "iterate.hpp", "device_common.hpp", "fofse_kernel.h")
-TRAFFIC = {"sources_sha256_16": "efec79943d9045a7", "blocks": 12864,
-           "fetch_kib": 91509.2, "write_kib": 67624.6, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "0561962f8fc61b3e", "blocks": 12864,
+           "fetch_kib": 73022.9, "write_kib": 79330.2, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # FP64 instruction counters of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU_FMA_F64
-# SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64), mean per dispatch on the same batch.
-COUNTERS = {"sources_sha256_16": "", "blocks": 12864, "flop": None}
+# SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 with four more SQ counters, ``bench.py
+# --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame --mixed 2048 --tune 0
+# --jobs 1``), per dispatch on the same batch: FMA 434,005,852, ADD 213,030,048,
+# MUL 102,321,940 wave instructions.
+COUNTERS = {"sources_sha256_16": "0561962f8fc61b3e", "blocks": 12864, "flop": 75735276288.0}
 
 
 def measured_traffic(n_blocks: int):
