@@ -195,6 +195,7 @@ __global__ __launch_bounds__(1024) void k_group_scan(GroupArgs g) {
     if (tid == 0) {
         g.counts[0] = all;                            // grouped items
         g.counts[1] = all + *g.n_single;              // all items
+        g.counts[2] = 0;                              // next item of the main kernel's queue
     }
 }
 
@@ -332,6 +333,7 @@ struct GroupShared {
     Xchg<kWavesG> xchg[kGroup][2];
     int flags[kGroup];
     int asym;                              // the item's w is not point-symmetric
+    int next;                              // next work item of the workgroup
 };
 
 // One work item (up to kGroup blocks of one mask class) as seen by wave WI of
@@ -491,18 +493,37 @@ __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(K
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
     for (int i = tid; i < 2 * T; i += NT) sh.ht[i] = p.htw[i];
 
-    // items of this workgroup: a contiguous range
-    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
-    const int per = (n_items + g.n_wg - 1) / g.n_wg;
-    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
-    const int i1 = min(n_items, i0 + per);
-
-    for (int item = i0; item < i1; ++item) {
+    auto run = [&](int item) {
         if constexpr (kWavesG == 1) {
             process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
         } else {
             if (wi == 0) process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
             else         process_item<T, 1, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
+        }
+    };
+    if (g.direct) {
+        // every block has the same support, so every item costs the same:
+        // contiguous ranges
+        const int n_items = (p.n_blocks + kGroup - 1) / kGroup;
+        const int per = (n_items + g.n_wg - 1) / g.n_wg;
+        const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+        const int i1 = min(n_items, i0 + per);
+        for (int item = i0; item < i1; ++item) run(item);
+    } else {
+        // items differ in cost (a point-symmetric mask takes about two thirds
+        // of the time of another): a queue, the counter zeroed by the
+        // grouping; the next index is fetched while the current item runs
+        const int n_items = g.counts[1];
+        if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
+        __syncthreads();
+        int item = sh.next;
+        while (item < n_items) {
+            int nxt = 0;
+            if (tid == 0) nxt = atomicAdd(&g.counts[2], 1);
+            run(item);
+            if (tid == 0) sh.next = nxt;        // every read of the last index preceded run's barriers
+            __syncthreads();
+            item = sh.next;
         }
     }
 }

@@ -97,8 +97,8 @@ def test_mixed_class_128_forward(frame_img, waves):
 @pytest.mark.parametrize("path", ["split", "grouped"])
 def test_128_irregular_masks_and_flags(frame_img, path):
     """T = 128 with irregular support masks, a block without support, a NaN
-    known sample, and the adjoint reporting the size as unsupported.  Blocks 0
-    and 2 share a mask (on the grouped path a live block next to a flagged
+    known sample, and the adjoint of the record (zero for the flagged blocks).
+    Blocks 0 and 2 share a mask (on the grouped path a live block next to a flagged
     one), as do blocks 3 and 4; block 1 is alone."""
     from paper_2207_01205_amd import fofse as F
     block, support, T, K = synth.MIXED_CLASSES[3]
@@ -130,11 +130,25 @@ def test_128_irregular_masks_and_flags(frame_img, path):
     same = np.all(sel[ok_blocks] == ref.keys, axis=1)
     err = np.abs(out[ok_blocks] - ref.g.reshape(3, -1)[:, target.reshape(-1) == 1]).max(axis=1)
     assert np.all(err[same] <= 1e-3)
-    with pytest.raises(F.FofseError):
-        plan.backward(torch.from_numpy(areas).to(dev), torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev),
-                      torch.zeros((5, 60), dtype=torch.int32, device=dev),
-                      torch.zeros((5, 60, 2), dtype=torch.float64, device=dev),
-                      torch.zeros((5, plan.nB), dtype=torch.float32, device=dev))
+    # the adjoint of the same record: zero for the flagged blocks, the oracle
+    # adjoint's for the others
+    gbar = np.random.default_rng(6).normal(size=(5, plan.nB)).astype(np.float32)
+    ga, _, gb = plan.backward(torch.from_numpy(areas).to(dev),
+                              torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev),
+                              torch.from_numpy(sel).to(dev), coef,
+                              torch.from_numpy(gbar).to(dev), known=torch.from_numpy(known).to(dev), per_block=True)
+    torch.cuda.synchronize()
+    ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+    assert np.all(ga[[1, 2]] == 0) and np.all(gb[[1, 2]] == 0)
+    tb = target.astype(bool)
+    for j, b in enumerate(ok_blocks):
+        gfull = np.zeros(target.shape)
+        gfull[tb] = gbar[b]
+        adj = fofse_adjoint(f[j], kn[j], T, 0.8, 0.5, sel[b], gfull)
+        scale = np.abs(adj.f_bar).max()
+        assert np.abs(ga[b] - adj.f_bar).max() <= 1e-6 * scale
+        assert gb[b, 0] == pytest.approx(adj.rho_bar, rel=1e-6)
+        assert gb[b, 1] == pytest.approx(adj.gamma_bar, rel=1e-6)
 
 
 def test_mixed_batch_graph_and_autotune(frame_img):
