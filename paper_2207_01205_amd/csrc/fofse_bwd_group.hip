@@ -128,6 +128,7 @@ struct BwdGroupShared {
     double2 tw[64];             // exp(-j 2 pi q / 64)
     double2 tw32[32];           // exp(-j 2 pi q / 32)
     int expo[kGroup];
+    int next;                   // next work item of the workgroup (queue)
     uint8_t mask[64 * 64];      // support mask of the work item's blocks
 };
 
@@ -258,12 +259,22 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
     for (int i = tid; i < 32; i += NT) sh.tw32[i] = p.twiddle[2 * i];
 
+    // work items: contiguous ranges when every block has the same support,
+    // else a queue (the counter zeroed by the grouping; the next index is
+    // fetched while the current item runs)
     const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
     const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
-    const int i1 = min(n_items, i0 + per);
-
-    for (int item = i0; item < i1; ++item) {
+    const int i1 = g.direct ? min(n_items, i0 + per) : n_items;
+    int item = i0;
+    if (!g.direct) {
+        if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
+        __syncthreads();
+        item = sh.next;
+    }
+    while (item < i1) {
+        int nxt = 0;
+        if (!g.direct && tid == 0) nxt = atomicAdd(&g.counts[2], 1);
         int nblk, b0, b1, b2, b3;
         if (g.direct) {
             nblk = min(kGroup, p.n_blocks - item * kGroup);
@@ -519,6 +530,13 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
                     p.grad_block[2 * bj + 1] = 0.0;
                 }
             }
+        }
+        if (g.direct) {
+            ++item;
+        } else {
+            if (tid == 0) sh.next = nxt;        // every read of the last index preceded the item's barriers
+            __syncthreads();
+            item = sh.next;
         }
     }
 }

@@ -607,6 +607,7 @@ struct Shared128G {
     Xchg<kWaves128G> xchg[kBlocks128G][2];
     int flags[kBlocks128G];
     int asym;                           // the item's w is not point-symmetric
+    int next;                           // next work item of the workgroup (queue)
 };
 static_assert(VROWS128 * T128 * sizeof(double) <= ROWS128 * T128 * sizeof(double2), "V window fits the row half");
 
@@ -719,17 +720,35 @@ __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128
     const bool params_ok = param_ok(rho) && param_ok(gamma);
     for (int i = tid; i < T128; i += NT) sh.tw[i] = p.twiddle[i];
     for (int i = tid; i < 2 * T128; i += NT) sh.ht[i] = p.htw[i];
-    // items of this workgroup: a contiguous range
+    // work items: contiguous ranges when every block has the same support
+    // (every item costs the same), else a queue, since point-symmetric items
+    // run a cheaper iteration (the counter zeroed by the grouping; the next
+    // index is fetched while the current item runs)
     const int n_items = g.direct ? (p.n_blocks + kBlocks128G - 1) / kBlocks128G : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
     const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
-    const int i1 = min(n_items, i0 + per);
+    const int i1 = g.direct ? min(n_items, i0 + per) : n_items;
     static_assert(kWaves128G == 4, "one instance per wave of a block");
-    for (int item = i0; item < i1; ++item) {
+    int item = i0;
+    if (!g.direct) {
+        if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
+        __syncthreads();
+        item = sh.next;
+    }
+    while (item < i1) {
+        int nxt = 0;
+        if (!g.direct && tid == 0) nxt = atomicAdd(&g.counts[2], 1);
         if (wi == 0) item128<0>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
         else if (wi == 1) item128<1>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
         else if (wi == 2) item128<2>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
         else item128<3>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        if (g.direct) {
+            ++item;
+        } else {
+            if (tid == 0) sh.next = nxt;        // every read of the last index preceded the item's barriers
+            __syncthreads();
+            item = sh.next;
+        }
     }
 }
 
