@@ -493,35 +493,34 @@ __global__ __launch_bounds__(kGroup * kWavesG * 64, 2) void fofse_group_kernel(K
     for (int i = tid; i < T; i += NT) sh.tw[i] = p.twiddle[i];
     for (int i = tid; i < 2 * T; i += NT) sh.ht[i] = p.htw[i];
 
-    auto run = [&](int item) {
+    // work items: contiguous ranges when every block has the same support
+    // (every item costs the same), else a queue, since items differ in cost (a
+    // point-symmetric mask takes about two thirds of the time of another): the
+    // counter is zeroed by the grouping, and the next index is fetched while
+    // the current item runs
+    const int n_items = g.direct ? (p.n_blocks + kGroup - 1) / kGroup : g.counts[1];
+    const int per = (n_items + g.n_wg - 1) / g.n_wg;
+    const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
+    const int i1 = g.direct ? min(n_items, i0 + per) : n_items;
+    int item = i0;
+    if (!g.direct) {
+        if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
+        __syncthreads();
+        item = sh.next;
+    }
+    while (item < i1) {
+        int nxt = 0;
+        if (!g.direct && tid == 0) nxt = atomicAdd(&g.counts[2], 1);
         if constexpr (kWavesG == 1) {
             process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
         } else {
             if (wi == 0) process_item<T, 0, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
             else         process_item<T, 1, MAXPX, FULL>(sh, p, g, item, tid, lane, jblk, tib, params_ok, rho, gamma);
         }
-    };
-    if (g.direct) {
-        // every block has the same support, so every item costs the same:
-        // contiguous ranges
-        const int n_items = (p.n_blocks + kGroup - 1) / kGroup;
-        const int per = (n_items + g.n_wg - 1) / g.n_wg;
-        const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
-        const int i1 = min(n_items, i0 + per);
-        for (int item = i0; item < i1; ++item) run(item);
-    } else {
-        // items differ in cost (a point-symmetric mask takes about two thirds
-        // of the time of another): a queue, the counter zeroed by the
-        // grouping; the next index is fetched while the current item runs
-        const int n_items = g.counts[1];
-        if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
-        __syncthreads();
-        int item = sh.next;
-        while (item < n_items) {
-            int nxt = 0;
-            if (tid == 0) nxt = atomicAdd(&g.counts[2], 1);
-            run(item);
-            if (tid == 0) sh.next = nxt;        // every read of the last index preceded run's barriers
+        if (g.direct) {
+            ++item;
+        } else {
+            if (tid == 0) sh.next = nxt;        // every read of the last index preceded the item's barriers
             __syncthreads();
             item = sh.next;
         }
