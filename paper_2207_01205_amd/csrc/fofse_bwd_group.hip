@@ -128,6 +128,8 @@ struct BwdGroupShared {
     double2 tw[64];             // exp(-j 2 pi q / 64)
     double2 tw32[32];           // exp(-j 2 pi q / 32)
     int expo[kGroup];
+    int live[kGroup];           // block slot takes part (present, no flag)
+    double rpart[kGroup][64];   // rho_hat terms of dL/df a helper wavefront found, per slot and lane
     int next;                   // next work item of the workgroup (queue)
     uint8_t mask[64 * 64];      // support mask of the work item's blocks
 };
@@ -386,6 +388,7 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         __syncthreads();
         if (params_ok && !(W0 > 0.0)) flags |= FOFSE_BLOCK_NO_SUPPORT;
         const bool live = present && flags == 0;
+        if (lane == 0) sh.live[wave] = live ? 1 : 0;     // read after the output pass's first barrier
         const double hW = (params_ok && W0 > 0.0) ? 0.5 * gamma / W0 : 0.0;
         // Z' = hW Z, each row k rotated by 13 k columns (the skewed layout above);
         // one wavefront per row: its lanes read the row before any writes it
@@ -485,39 +488,53 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
             fft_stage_b<T, NT>(sh.buf, 32, 1, 32, tidv);
             fft_stage_b<T, NT>(sh.buf + 2048, 32, 1, 32, tidv);
             __syncthreads();
-            if (mine && present) {
-                // dL/df = w (w f)bar on A; rho term of R0 = DFT(w f); kBatch
-                // samples per lane in flight
-                const double2* zg = sh.buf + grid * 2048;
-                for (int i0 = lane; i0 < MN; i0 += 64 * kBatch) {
-                    double w[kBatch], dw[kBatch];
-                    float x[kBatch];
+            // dL/df = w (w f)bar on A and the rho term of R0 = DFT(w f) for the
+            // two blocks of the pass, each by its own wavefront and one of the
+            // other pass (every other group of 64 samples); the helper's rho
+            // terms go to rpart.  kBatch samples per lane in flight.
+            {
+                const int slot = 2 * pp + (wave & 1);
+                const int help = (wave >> 1) != pp ? 1 : 0;
+                if (slot < nblk) {
+                    const int bs = slot == 0 ? b0 : slot == 1 ? b1 : slot == 2 ? b2 : b3;
+                    const size_t abs = (size_t)bs * MN;
+                    const bool lv = sh.live[slot] != 0;
+                    const double2* zg = sh.buf + (slot & 1) * 2048;
+                    double rr = 0.0;
+                    for (int i0 = lane + 64 * help; i0 < MN; i0 += 128 * kBatch) {
+                        double w[kBatch], dw[kBatch];
+                        float x[kBatch];
 #pragma unroll
-                    for (int u = 0; u < kBatch; ++u) {
-                        const int i = i0 + 64 * u;
-                        const bool in = live && i < MN;
-                        w[u] = in ? p.wtab[i] : 0.0;
-                        dw[u] = in ? p.dwtab[i] : 0.0;
-                        x[u] = in ? p.areas[ab + i] : 0.0f;
-                    }
+                        for (int u = 0; u < kBatch; ++u) {
+                            const int i = i0 + 128 * u;
+                            const bool in = lv && i < MN;
+                            w[u] = in ? p.wtab[i] : 0.0;
+                            dw[u] = in ? p.dwtab[i] : 0.0;
+                            x[u] = in ? p.areas[abs + i] : 0.0f;
+                        }
 #pragma unroll
-                    for (int u = 0; u < kBatch; ++u) {
-                        const int i = i0 + 64 * u;
-                        if (i < MN) {
-                            float gv = 0.0f;
-                            if (live && sh.mask[i]) {
-                                const int m = i / N, n = i - m * N;
-                                const double2 v = zg[FftPlan<T>::perm(m) * 32 + FftPlan<32>::perm(n >> 1)];
-                                const double wfb = (n & 1) ? v.y : v.x;
-                                gv = (float)(w[u] * wfb);
-                                racc += dw[u] * (double)x[u] * wfb;
+                        for (int u = 0; u < kBatch; ++u) {
+                            const int i = i0 + 128 * u;
+                            if (i < MN) {
+                                float gv = 0.0f;
+                                if (lv && sh.mask[i]) {
+                                    const int m = i / N, n = i - m * N;
+                                    const double2 v = zg[FftPlan<T>::perm(m) * 32 + FftPlan<32>::perm(n >> 1)];
+                                    const double wfb = (n & 1) ? v.y : v.x;
+                                    gv = (float)(w[u] * wfb);
+                                    rr += dw[u] * (double)x[u] * wfb;
+                                }
+                                if (p.grad_areas) p.grad_areas[abs + i] = gv;
                             }
-                            if (p.grad_areas) p.grad_areas[ab + i] = gv;
                         }
                     }
+                    if (help) sh.rpart[slot][lane] = rr;
+                    else racc += rr;
                 }
             }
         }
+        __syncthreads();                         // the helpers' rho terms are in rpart
+        if (present) racc += sh.rpart[wave][lane];
         if (present) {
             racc = wave_sum(racc);
             tacc = wave_sum(tacc);
