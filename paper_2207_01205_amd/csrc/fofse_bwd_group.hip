@@ -131,7 +131,7 @@ struct BwdGroupShared {
     int live[kGroup];           // block slot takes part (present, no flag)
     double rpart[kGroup][64];   // rho_hat terms of dL/df a helper wavefront found, per slot and lane
     int next;                   // next work item of the workgroup (queue)
-    uint8_t mask[64 * 64];      // support mask of the work item's blocks
+    alignas(16) uint8_t mask[64 * 64];   // support mask of the work item's blocks
 };
 
 // Serial sweep of chunk r: row j (from the last) is final when reached; it is
@@ -315,19 +315,46 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         // per wavefront: flags, record, cbar0
         int flags = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
         if (present) {
-            // kBatch samples per lane in flight
             bool bad = false;
-            for (int i0 = lane; i0 < MN; i0 += 64 * kBatch) {
-                uint32_t x[kBatch];
+            if ((MN & 3) == 0 && (((uintptr_t)p.areas) & 15) == 0) {
+                // four samples per 16-byte load, kQuad loads per lane in flight
+                constexpr int kQuad = 12;
+                const uint4* a4 = reinterpret_cast<const uint4*>(p.areas + ab);
+                const uint32_t* m4 = reinterpret_cast<const uint32_t*>(sh.mask);
+                const int nq = MN >> 2;
+                for (int q0 = lane; q0 < nq; q0 += 64 * kQuad) {
+                    uint4 x[kQuad];
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int i = i0 + 64 * u;
-                    x[u] = i < MN ? sample_bits(p.areas, ab + i) : 0u;
+                    for (int u = 0; u < kQuad; ++u) {
+                        const int q = q0 + 64 * u;
+                        x[u] = q < nq ? a4[q] : make_uint4(0u, 0u, 0u, 0u);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kQuad; ++u) {
+                        const int q = q0 + 64 * u;
+                        if (q < nq) {
+                            const uint32_t mk = m4[q];    // the four mask bytes of these samples
+                            bad |= (mk & 0xFFu) && nonfinite_bits(x[u].x);
+                            bad |= (mk & 0xFF00u) && nonfinite_bits(x[u].y);
+                            bad |= (mk & 0xFF0000u) && nonfinite_bits(x[u].z);
+                            bad |= (mk & 0xFF000000u) && nonfinite_bits(x[u].w);
+                        }
+                    }
                 }
+            } else {
+                // kBatch samples per lane in flight
+                for (int i0 = lane; i0 < MN; i0 += 64 * kBatch) {
+                    uint32_t x[kBatch];
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int i = i0 + 64 * u;
-                    if (i < MN && sh.mask[i]) bad |= nonfinite_bits(x[u]);
+                    for (int u = 0; u < kBatch; ++u) {
+                        const int i = i0 + 64 * u;
+                        x[u] = i < MN ? sample_bits(p.areas, ab + i) : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch; ++u) {
+                        const int i = i0 + 64 * u;
+                        if (i < MN && sh.mask[i]) bad |= nonfinite_bits(x[u]);
+                    }
                 }
             }
             if (__any(bad)) flags |= FOFSE_BLOCK_NONFINITE;
