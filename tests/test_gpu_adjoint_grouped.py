@@ -188,3 +188,29 @@ def test_backward_ignores_imaginary_part_of_self_conjugate_coefficients(frame_ar
     ga2, grg2, gb2 = gpu_backward(plan, A.areas[sub], A.known[sub], 0.8, 0.5, ref.keys, coef2, gbar_b,
                                   f"{path} imaginary parts on self-conjugate classes")
     assert np.array_equal(ga, ga2) and np.array_equal(gb, gb2) and np.array_equal(grg, grg2)
+
+
+def test_grouped_backward_queue_many_items_per_workgroup():
+    """The grouped adjoint over far more work items than resident workgroups
+    (4 frames, one workgroup per CU, items from a queue): two runs and the same
+    blocks in a small batch give the same bits."""
+    frames = [synth.frame_concealment(30 + i, 40 + i) for i in range(4)]
+    areas = np.concatenate([f.areas for f in frames])
+    known = np.concatenate([f.known for f in frames])
+    target = frames[0].target
+    n, K = areas.shape[0], 80
+    rng = np.random.default_rng(17)
+    keys = rng.integers(0, 64 * 64, size=(n, K)).astype(np.int32)
+    coef = rng.normal(size=(n, K)) + 1j * rng.normal(size=(n, K))
+    gbar_b = rng.normal(size=(n, int(target.sum()))).astype(np.float32)
+    plan = _grouped(48, 48, K, target)
+    plan.set_occupancy(1)
+    r1 = gpu_backward(plan, areas, known, 0.8, 0.5, keys, coef, gbar_b, "queue run 1")
+    r2 = gpu_backward(plan, areas, known, 0.8, 0.5, keys, coef, gbar_b, "queue run 2")
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+    lo = 1700
+    part = gpu_backward(plan, areas[lo:lo + 150], known[lo:lo + 150], 0.8, 0.5, keys[lo:lo + 150],
+                        coef[lo:lo + 150], gbar_b[lo:lo + 150], "queue, small batch")
+    assert np.array_equal(r1[0][lo:lo + 150], part[0])
+    assert np.array_equal(r1[2][lo:lo + 150], part[2])

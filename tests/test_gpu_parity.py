@@ -272,3 +272,24 @@ def test_grouped_result_does_not_depend_on_the_batch(T):
     inv = np.argsort(shuffled)
     for x, y in zip(full, mixed):
         assert np.array_equal(x, y[inv])
+
+
+@pytest.mark.parametrize("T", [64, 128])
+def test_grouped_queue_many_items_per_workgroup(T):
+    """Far more work items than resident workgroups (4 frames, one workgroup
+    per CU): the items come from a queue, so which workgroup takes which item
+    changes from run to run; the bits must not.  The same blocks in small
+    batches (other queues, other work-item partners) give the same bits."""
+    frames = [synth.frame_concealment(10 + i, 20 + i) for i in range(4)]
+    areas = np.concatenate([f.areas for f in frames])
+    known = np.concatenate([f.known for f in frames])
+    plan = _plan(48, 48, T, 80, frames[0].target, "grouped")
+    plan.set_occupancy(1)
+    r1 = run_gpu(plan, areas, known, 0.8, 0.5, f"T={T} 4 frames, run 1")
+    r2 = run_gpu(plan, areas, known, 0.8, 0.5, f"T={T} 4 frames, run 2")
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+    for lo in (0, 1500, 3000):
+        part = run_gpu(plan, areas[lo:lo + 200], known[lo:lo + 200], 0.8, 0.5, f"T={T} blocks {lo}-{lo + 199}")
+        for x, y in zip(r1, part):
+            assert np.array_equal(x[lo:lo + 200], y)
