@@ -286,8 +286,8 @@ constexpr int Q128 = 32;
 constexpr int VROWS128 = 3 * Q128 + 1 + Q128;     // rows -32 .. 96
 
 // The V window from the row half of W (natural column order) in spec, in place.
-// Round 1 computes rows a = -32 and a = 32 .. 96, which read W rows 32 .. 64
-// only, and writes a = 32 .. 96 (the bytes of W rows 32 .. 64); round 2 computes
+// Pass 1 computes rows a = -32 and a = 32 .. 96, which read W rows 32 .. 64
+// only, and writes a = 32 .. 96 (the bytes of W rows 32 .. 64); pass 2 computes
 // a = -31 .. 31 from W rows 0 .. 31 and writes a = -32 .. 31.
 template <int NT>
 __device__ __forceinline__ void build_v128(double2* spec, const double2* ht, int R0, int C0, int tid) {
@@ -304,7 +304,7 @@ __device__ __forceinline__ void build_v128(double2* spec, const double2* ht, int
         const double2 P = ht[(a * R0 + b * C0) & (2 * T128 - 1)];
         return P.x * w.x + P.y * w.y;             // Re(conj(P) W)
     };
-    // round 1: a = 32 .. 96 (65 rows) and a = -32 (kept for round 2)
+    // pass 1: a = 32 .. 96 (65 rows) and a = -32 (kept for pass 2)
     constexpr int N1 = 65 * T128, E1 = (N1 + NT - 1) / NT;
     constexpr int E0 = (T128 + NT - 1) / NT;
     double v1[E1], v0[E0];
@@ -325,7 +325,7 @@ __device__ __forceinline__ void build_v128(double2* spec, const double2* ht, int
         if (idx < N1) vw[(32 + Q128) * T128 + idx] = v1[e];
     }
     __syncthreads();
-    // round 2: a = -31 .. 31 (63 rows), W rows 0 .. 31 are intact
+    // pass 2: a = -31 .. 31 (63 rows), W rows 0 .. 31 are intact
     constexpr int N2 = 63 * T128, E2 = (N2 + NT - 1) / NT;
     double v2[E2];
 #pragma unroll
