@@ -358,6 +358,11 @@ __device__ __forceinline__ void run_wave128_sym(RegSpec<row_begin128<NW>(WI + 1)
     const int K = p.K;
     const int RR = p.N - 1, CC = p.M - 1;       // transposed placement
     const bool odd_r = (RR & 1) != 0, odd_c = (CC & 1) != 0;
+    // reference slots of the four read forms (see rd below)
+    constexpr int r1d = k0 > Q ? k0 : Q;                  // V1 direct: slots k >= Q
+    constexpr int r1m = k0 + S - 1 < Q - 1 ? k0 + S - 1 : Q - 1;   // V1 mirrored: k < Q
+    constexpr int r2d = k0;                               // V2 direct: k <= Q
+    constexpr int r2m = k0 + S - 1;                       // V2 mirrored: k > Q
     int u = 0, v = 0;
     double ca = 0.0, cb = 0.0;
     for (int it = 0; it < K; ++it) {
@@ -382,12 +387,21 @@ __device__ __forceinline__ void run_wave128_sym(RegSpec<row_begin128<NW>(WI + 1)
             A2m[h] = n2m ? ca : -ca; B2m[h] = n2m ? -cb : cb;
         }
         // window rows: W1 direct a = k - u, mirrored u - k; W2 direct k + u,
-        // mirrored 128 - k - u (window row = a + 32)
+        // mirrored 128 - k - u (window row = a + 32).  Each read form has one
+        // base per column half at the wave's slot of lowest row (the smallest k
+        // for a direct form, the largest for a mirrored one), so that every
+        // slot reads at a compile-time offset above it.
+        const double* bs1d[2], *bs1m[2], *bs2d[2], *bs2m[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bs1d[h] = vw + (r1d - u + Q) * T128 + col[h][0];
+            bs1m[h] = vw + (u - r1m + Q) * T128 + col[h][1];
+            bs2d[h] = vw + (r2d + u + Q) * T128 + col[h][2];
+            bs2m[h] = vw + (T128 - r2m - u + Q) * T128 + col[h][3];
+        }
         auto rd = [&](int k, int h, double& V1, double& V2) {
-            const int r1 = k >= Q ? k - u : u - k;
-            const int r2 = k <= Q ? k + u : T128 - k - u;
-            V1 = vw[(r1 + Q) * T128 + col[h][k >= Q ? 0 : 1]];
-            V2 = vw[(r2 + Q) * T128 + col[h][k <= Q ? 2 : 3]];
+            V1 = k >= Q ? bs1d[h][(k - r1d) * T128] : bs1m[h][(r1m - k) * T128];
+            V2 = k <= Q ? bs2d[h][(k - r2d) * T128] : bs2m[h][(r2m - k) * T128];
         };
         constexpr int CH = 2;
         constexpr int NC = (S + CH - 1) / CH;

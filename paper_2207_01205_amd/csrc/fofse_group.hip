@@ -311,16 +311,53 @@ __device__ __forceinline__ void fft64_stage_b_to_pairs(double2* win, const doubl
 
 constexpr int kWavesG = 1;                  // waves per block in the grouped path
 
+// A zero 16-byte LDS entry whose value is made where it is stored: a zero
+// register tuple kept live across the transforms gets spilled, and its reload
+// then waits for every global load in flight (loads complete in order).
+__device__ __forceinline__ void store_zero16(double2* dst) {
+    uint32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    *reinterpret_cast<uint4*>(dst) = make_uint4(z, z, z, z);
+}
+
+// Row stride (16-byte entries) of the per-block transform grid: one entry more
+// than a row, so that entry (n, m) and (n + 1, m) lie on different LDS banks.
+// 64 rows of 65 entries fill the window exactly.
+constexpr int kGridStride64 = 65;
+
 template <int T, int WI>
 __device__ __forceinline__ void extract_rows(const double2* win, int lane,
                                              RegSpec<WaveRows<T, kWavesG, WI>::S>& R) {
     using WR = WaveRows<T, kWavesG, WI>;
+    constexpr int S = kGridStride64;
 #pragma unroll
     for (int s = 0; s < WR::S; ++s) {
         const int k = WR::k0 + s;
         double2 a = make_double2(0.0, 0.0);
-        if (lane < T) a = win[FftPlan<T>::perm(k) * T + FftPlan<T>::perm(lane)];
+        if (lane < T) a = win[FftPlan<T>::perm(k) * S + FftPlan<T>::perm(lane)];
         R.set(s, a.x, a.y);
+    }
+}
+
+// Stage B of a 64-point FFT along contiguous lines of a grid with row stride
+// kGridStride64: the eight lanes of a group take eight consecutive lines at
+// the same k1, so their reads and writes fall on different banks (with a
+// lane per k1 of one line they all met the same ones).  Lines run up to
+// nlines rounded up to a multiple of 8; the extra lines must hold zeros.
+template <int NT>
+__device__ __forceinline__ void fft64_stage_b_rows(double2* buf, int nlines, int tid) {
+    constexpr int S = kGridStride64;
+    const int ntask = ((nlines + 7) & ~7) * 8;
+    for (int task = tid; task < ntask; task += NT) {
+        const int line = (task & 7) | ((task >> 6) << 3);
+        const int k1 = (task >> 3) & 7;
+        double2* base = buf + line * S + 8 * k1;
+        double2 x[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) x[n2] = base[n2];
+        dft8(x);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) base[k2] = x[k2];
     }
 }
 
@@ -366,23 +403,48 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     if (tid == 0) sh.asym = 0;
 
     // weights of this thread's samples (eqs. 4, 15): identical for the item
+    // (every load issued before any is used, indices clamped into the area)
     double wreg[MAXPX];
+    {
+        uint8_t off[MAXPX];                 // sample beyond the area, on B or unknown
 #pragma unroll
-    for (int q = 0; q < MAXPX; ++q) {
-        const int i = tid + q * NT;
-        wreg[q] = 0.0;
-        if (i < MN && eff_known(g.known, p.target, (size_t)b_rep * MN, i)) wreg[q] = p.wtab[i];
+        for (int q = 0; q < MAXPX; ++q) {
+            const int i = min(tid + q * NT, MN - 1);
+            wreg[q] = p.wtab[i];
+            off[q] = p.target[i];
+        }
+        if (g.known) {
+            uint8_t kn[MAXPX];
+#pragma unroll
+            for (int q = 0; q < MAXPX; ++q) kn[q] = g.known[(size_t)b_rep * MN + min(tid + q * NT, MN - 1)];
+#pragma unroll
+            for (int q = 0; q < MAXPX; ++q) off[q] |= kn[q] == 0;
+        }
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q)
+            if (tid + q * NT >= MN || off[q] != 0) wreg[q] = 0.0;
     }
 
     // R = DFT(w f) of each block by its own transform (eqs. 7, 8), so that a
-    // block's result does not depend on which blocks share its work item
+    // block's result does not depend on which blocks share its work item.
+    // The grid is transposed (entry (n, m) holds area sample (m, n)) with row
+    // stride kGridStride64; rows n >= N and entries m >= M are zero.
+    constexpr int S = kGridStride64;
+    static_assert(T == 64 && S == T + 1, "the transform grid (T rows of T + 1 entries) fills the window");
     RegSpec<WaveRows<T, kWavesG, WI>::S> R;
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
         if (j >= nblk) break;                  // uniform over the workgroup
+        // this thread's samples of the block, all loads issued before any is
+        // used (indices clamped into the area, samples beyond it dropped)
+        uint32_t xs[MAXPX];
+#pragma unroll
+        for (int q = 0; q < MAXPX; ++q) xs[q] = sample_bits(p.areas, (size_t)blk[j] * MN + min(tid + q * NT, MN - 1));
         __syncthreads();
-        for (int i = tid; i < T * T; i += NT) win[i] = make_double2(0.0, 0.0);
-        __syncthreads();
+        for (int e = tid; e < T * T; e += NT) {
+            const int n = e >> 6, m = e & (T - 1);
+            if (n >= N || m >= M) store_zero16(&win[e + n]);       // n S + m with S = T + 1
+        }
 #pragma unroll
         for (int q = 0; q < MAXPX; ++q) {
             const int i = tid + q * NT;
@@ -390,29 +452,31 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
                 const int m = i / N, n = i - m * N;
                 double fw = 0.0;
                 if (wreg[q] != 0.0) {
-                    const uint32_t xb = sample_bits(p.areas, (size_t)blk[j] * MN + i);
-                    if (nonfinite_bits(xb)) atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
-                    else fw = wreg[q] * (double)__uint_as_float(xb);
+                    if (nonfinite_bits(xs[q])) atomicOr(&sh.flags[j], FOFSE_BLOCK_NONFINITE);
+                    else fw = wreg[q] * (double)__uint_as_float(xs[q]);
                 }
-                win[n * T + m] = make_double2(fw, 0.0);        // transposed placement
+                win[n * S + m] = make_double2(fw, 0.0);
             }
         }
         __syncthreads();
-        fft_stage_a<T, NT>(win, sh.tw, N, T, 1, tid);
+        fft_stage_a<T, NT>(win, sh.tw, N, S, 1, tid);
         __syncthreads();
-        fft_stage_b<T, NT>(win, N, T, 1, tid);
+        fft64_stage_b_rows<NT>(win, N, tid);
         __syncthreads();
-        fft_stage_a<T, NT>(win, sh.tw, T, 1, T, tid);
+        fft_stage_a<T, NT>(win, sh.tw, T, 1, S, tid);
         __syncthreads();
-        fft_stage_b<T, NT>(win, T, 1, T, tid);
+        fft_stage_b<T, NT>(win, T, 1, S, tid);
         __syncthreads();
         if (jblk == j) extract_rows<T, WI>(win, lane, R);
     }
 
-    // W = DFT(w) straight into the window (rows -T/4 .. 3T/4)
+    // W = DFT(w) straight into the window (rows -T/4 .. 3T/4), from the
+    // transposed grid with row stride T (rows n >= N and entries m >= M zero)
     __syncthreads();
-    for (int i = tid; i < T * T; i += NT) win[i] = make_double2(0.0, 0.0);
-    __syncthreads();
+    for (int e = tid; e < T * T; e += NT) {
+        const int n = e >> 6, m = e & (T - 1);
+        if (n >= N || m >= M) store_zero16(&win[e]);
+    }
 #pragma unroll
     for (int q = 0; q < MAXPX; ++q) {
         const int i = tid + q * NT;
