@@ -39,6 +39,32 @@ constexpr int ROWS128 = H128 + 1;
 template <int NW>
 __host__ __device__ constexpr int row_begin128(int w) { return (w * ROWS128 + NW - 1) / NW; }
 
+// A wave's rows of R, one register pair per slot: the first 16 slots in one
+// vector, the rest in a second (no padding slot: a 17-row wave has no
+// registers to spare).
+template <int S>
+struct RowRegs {
+    static constexpr int CA = S > 16 ? 16 : S;
+    static constexpr int CB = S > 16 ? S - 16 : 1;
+    static_assert(S <= 32, "at most two chunks");
+    typedef double va __attribute__((ext_vector_type(CA)));
+    typedef double vb __attribute__((ext_vector_type(CB)));
+    va re0, im0;
+    vb re1, im1;
+    __device__ __forceinline__ double gr(int s) const { return s < CA ? re0[s] : re1[s - CA]; }
+    __device__ __forceinline__ double gi(int s) const { return s < CA ? im0[s] : im1[s - CA]; }
+    __device__ __forceinline__ void set(int s, double a, double c) {
+        if (s < CA) { re0[s] = a; im0[s] = c; } else { re1[s - CA] = a; im1[s - CA] = c; }
+    }
+    // (re, im) of slot s (uniform) in lane `lane` (uniform)
+    __device__ __forceinline__ double2 fetch(int s, int lane) const {
+        double a, c;
+        if (S <= 16 || s < CA) { a = readlane_f64(re0[s], lane); c = readlane_f64(im0[s], lane); }
+        else { a = readlane_f64(re1[s - CA], lane); c = readlane_f64(im1[s - CA], lane); }
+        return make_double2(a, c);
+    }
+};
+
 __device__ __forceinline__ int perm128(int k) { return FftPlan<T128>::perm(k & (T128 - 1)); }
 
 __device__ __forceinline__ double neg_if(bool c, double x) { return c ? -x : x; }
@@ -123,8 +149,8 @@ __device__ __forceinline__ void row_half_spectrum(double2* spec, const double2* 
 // runs the same barriers and writes nothing (a missing or flagged block that
 // shares the workgroup with a live one).
 template <int NW, int WI>
-__device__ __forceinline__ void run_wave128(RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
-                                            RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
+__device__ __forceinline__ void run_wave128(RowRegs<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
+                                            RowRegs<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
                                             const double2* Wb, Xchg<NW>* xchg, const KParams& p, int b,
                                             int lane, double gW0, bool live = true) {
     constexpr int k0 = row_begin128<NW>(WI);
@@ -348,8 +374,8 @@ __device__ __forceinline__ void build_v128(double2* spec, const double2* ht, int
 }
 
 template <int NW, int WI>
-__device__ __forceinline__ void run_wave128_sym(RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
-                                                RegSpec<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
+__device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R0,
+                                                RowRegs<row_begin128<NW>(WI + 1) - row_begin128<NW>(WI)>& R1,
                                                 const double* vw, const double2* ht, Xchg<NW>* xchg,
                                                 const KParams& p, int b, int lane, double gW0, bool live) {
     constexpr int k0 = row_begin128<NW>(WI);
@@ -529,7 +555,7 @@ __device__ __forceinline__ void wave128(Shared128<NW>& sh, const KParams& p, int
                                         double gamma, int flags_pre, FW wval) {
     constexpr int k0 = row_begin128<NW>(WI);
     constexpr int S = row_begin128<NW>(WI + 1) - k0;
-    RegSpec<S> R0, R1;
+    RowRegs<S> R0, R1;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double2* row = sh.spec + (k0 + s) * T128;
@@ -657,7 +683,7 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
     if (tid == 0) sh.asym = 0;
 
     // eqs. 4, 7, 8: R of each block by its own transform; its waves take their rows
-    RegSpec<S> R0, R1;
+    RowRegs<S> R0, R1;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         R0.set(s, 0.0, 0.0);
