@@ -678,6 +678,10 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
         if (p.known) a = a && p.known[rep + i] != 0;
         return a;
     };
+    // the thread index as an opaque per-item value: keeps the compiler from
+    // hoisting every per-thread index of the item's transforms out of the item
+    // loop (they would be spilled for the whole kernel and reloaded per item)
+    asm volatile("" : "+v"(tid), "+v"(lane));
     __syncthreads();                              // previous item done with LDS
     if (tid < kBlocks128G) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     if (tid == 0) sh.asym = 0;
