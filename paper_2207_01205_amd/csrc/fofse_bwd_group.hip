@@ -40,10 +40,6 @@ namespace {
 constexpr int kRC = kGroupBackwardMaxK / 64;   // row chunks per lane
 constexpr int kBatch = 6;                      // samples per lane with loads in flight
 
-__device__ __forceinline__ bool known_at(const uint8_t* known, const uint8_t* target, size_t base, int i) {
-    return target[i] == 0 && (known == nullptr || known[base + i] != 0);
-}
-
 // Z' is stored skewed: entry (k, l) at column (l + 13 k) mod 64 of row k, so
 // that the LDS bank of an entry depends on k as well as l (the classes of a
 // record cluster at low frequencies; unskewed, the gathers of a wave pile onto
@@ -199,16 +195,18 @@ __device__ __forceinline__ void cbar0_rows(const BParams& p, int bj, int lane, d
     const int N = p.N;
     const float* go = p.grad_out + (size_t)bj * p.nB;
     for (int m0 = 0; m0 < p.b_h; m0 += 16) {
+        // the 16 index loads, then the 16 value loads, each group in flight
+        // together (indices clamped into the box, values outside it dropped)
         float gv[16];
-        const int n = p.b_n0 + lane;
+        int qv[16];
+        const int n = p.b_n0 + min(lane, p.b_w - 1);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            gv[i] = 0.0f;
-            if (lane < p.b_w && m0 + i < p.b_h) {
-                const int q = p.bidx[(p.b_m0 + m0 + i) * N + n];
-                if (q >= 0) gv[i] = go[q];
-            }
-        }
+        for (int i = 0; i < 16; ++i) qv[i] = p.bidx[(p.b_m0 + min(m0 + i, p.b_h - 1)) * N + n];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gv[i] = go[max(qv[i], 0)];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (!(lane < p.b_w && m0 + i < p.b_h && qv[i] >= 0)) gv[i] = 0.0f;
         double2 h[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) h[i] = make_double2(0.0, 0.0);
@@ -304,11 +302,24 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         int tidv = tid;
         asm volatile("" : "+v"(tidv));
         __syncthreads();                         // previous item done with LDS
-        // the item's support mask, once for all its blocks
+        // the item's support mask, once for all its blocks (every load issued
+        // before any is used, indices clamped into the area)
+        {
+            uint8_t off[MAXPX];                  // on B or unknown
 #pragma unroll
-        for (int q = 0; q < MAXPX; ++q) {
-            const int i = tidv + q * NT;
-            if (i < MN) sh.mask[i] = known_at(p.known, p.target, (size_t)b_rep * MN, i) ? 1 : 0;
+            for (int q = 0; q < MAXPX; ++q) off[q] = p.target[min(tidv + q * NT, MN - 1)];
+            if (p.known) {
+                uint8_t kn[MAXPX];
+#pragma unroll
+                for (int q = 0; q < MAXPX; ++q) kn[q] = p.known[(size_t)b_rep * MN + min(tidv + q * NT, MN - 1)];
+#pragma unroll
+                for (int q = 0; q < MAXPX; ++q) off[q] |= kn[q] == 0;
+            }
+#pragma unroll
+            for (int q = 0; q < MAXPX; ++q) {
+                const int i = tidv + q * NT;
+                if (i < MN) sh.mask[i] = off[q] == 0 ? 1 : 0;
+            }
         }
         __syncthreads();
 
@@ -364,12 +375,13 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         for (int r = 0; r < kRC; ++r) {
             const int nu = lane + 64 * r;
             const bool valid = present && nu < K;
-            int key = 0;
-            double2 c = make_double2(0.0, 0.0);
-            if (valid) {
-                key = p.sel[(size_t)bj * K + nu] & (T * T - 1);
-                c = make_double2(p.coef[2 * ((size_t)bj * K + nu)], p.coef[2 * ((size_t)bj * K + nu) + 1]);
-            }
+            // loaded unconditionally (index clamped into the block's record) so
+            // that the loads of every row are in flight together
+            const size_t ri = (size_t)bj * K + min(nu, K - 1);
+            const int key_l = p.sel[ri];
+            const double2 c_l = make_double2(p.coef[2 * ri], p.coef[2 * ri + 1]);
+            const int key = valid ? key_l & (T * T - 1) : 0;
+            double2 c = valid ? c_l : make_double2(0.0, 0.0);
             R.x[r] = pack_class(key >> 6, key & 63);
             R.pr[r] = valid && packed_pair(R.x[r]);
             // a self-conjugate class has a real coefficient (the forward writes 0
@@ -380,15 +392,27 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         if (present && flags == 0) cbar0_rows(p, bj, lane, sh.buf + wave * 1024, sh.tw, R, K);
         __syncthreads();                         // H tables done
 
-        // Z = DFT(w + j dw/drho) of the item's mask, natural order
-        for (int i = tidv; i < T * T; i += NT) sh.buf[i] = make_double2(0.0, 0.0);
-        __syncthreads();
+        // Z = DFT(w + j dw/drho) of the item's mask, natural order: every sample
+        // of the area is written (0 off the support), the rest of the grid is
+        // cleared, and the table loads are all issued before any is used
+        {
+            double2 wz[MAXPX];
 #pragma unroll
-        for (int q = 0; q < MAXPX; ++q) {
-            const int i = tidv + q * NT;
-            if (i < MN && sh.mask[i]) {
-                const int m = i / N, n = i - m * N;
-                sh.buf[m * T + n] = make_double2(p.wtab[i], p.dwtab[i]);
+            for (int q = 0; q < MAXPX; ++q) {
+                const int i = min(tidv + q * NT, MN - 1);
+                wz[q] = make_double2(p.wtab[i], p.dwtab[i]);
+            }
+            for (int e = tidv; e < T * T; e += NT) {
+                const int m = e >> 6, n = e & (T - 1);
+                if (m >= M || n >= N) sh.buf[e] = make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < MAXPX; ++q) {
+                const int i = tidv + q * NT;
+                if (i < MN) {
+                    const int m = i / N, n = i - m * N;
+                    sh.buf[m * T + n] = sh.mask[i] ? wz[q] : make_double2(0.0, 0.0);
+                }
             }
         }
         __syncthreads();
