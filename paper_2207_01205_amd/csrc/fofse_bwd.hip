@@ -44,8 +44,10 @@
 
 namespace fofse {
 
+// Workgroups per CU: at T <= 32 the LDS of four fits and the kernel is bound by
+// latency, so four (128 VGPRs, with some spilling) run faster than two.
 template <int T, int KMAX>
-__global__ __launch_bounds__(256, KMAX <= 256 ? 2 : 1) void fofse_bwd_kernel(BParams p) {
+__global__ __launch_bounds__(256, KMAX <= 256 ? (T <= 32 ? 4 : 2) : 1) void fofse_bwd_kernel(BParams p) {
     constexpr int NT = 256;
     constexpr int CH = 256;                 // samples of B staged per pass
     using KY = Key<T>;
