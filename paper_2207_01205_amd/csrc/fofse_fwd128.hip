@@ -101,22 +101,56 @@ __device__ __forceinline__ void row_half_spectrum(double2* spec, const double2* 
         }
         if (a) *asym = 1;
     }
-    // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128), l = lg + NW j
+    // X1[l][m] = sum_n x[m][n] exp(-j 2 pi l n / 128) for l = 0..64, in two
+    // steps with n = 8 n1 + n2 (x[m][n] = 0 for n >= 64):
+    //   Y[n2][k][m] = sum_n1 x[m][8 n1 + n2] exp(-j 2 pi k n1 / 16), k = l mod 16,
+    //   a 16-point DFT of 8 samples (even k: DFT8 of x, odd k: DFT8 of x
+    //   exp(-j 2 pi n1 / 16)), one (m, n2) per thread;
+    //   X1[l][m] = sum_n2 exp(-j 2 pi l n2 / 128) Y[n2][l mod 16][m].
+    // Summing over n directly read a twiddle per (l, n) for every lane of a
+    // wave, and that broadcast traffic bounded the transform.
+    {
+        const int m1 = tid & 63, n2 = (tid >> 6) & 7;
+        const bool act = tid < 512;
+        double xv[8];
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) xv[n1] = act ? xs[(8 * n1 + n2) * 64 + m1] : 0.0;
+        __syncthreads();                                    // staging consumed
+        if (act) {
+            double2* Y = spec + n2 * 16 * 64 + m1;          // Y[(n2 16 + k) 64 + m]
+            double2 y[8];
+#pragma unroll
+            for (int n1 = 0; n1 < 8; ++n1) y[n1] = make_double2(xv[n1], 0.0);
+            dft8(y);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Y[(2 * q) * 64] = y[q];
+#pragma unroll
+            for (int n1 = 0; n1 < 8; ++n1) {
+                const double2 w = tw[8 * n1];               // exp(-j 2 pi n1 / 16)
+                y[n1] = make_double2(xv[n1] * w.x, xv[n1] * w.y);
+            }
+            dft8(y);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Y[(2 * q + 1) * 64] = y[q];
+        }
+        __syncthreads();
+    }
     const int m = tid & 63, lg = tid >> 6;
     double2 acc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[j] = make_double2(0.0, 0.0);
-    for (int n = 0; n < N; ++n) {
-        const double x = xs[n * 64 + m];
+#pragma unroll 1
+    for (int n2 = 0; n2 < 8; ++n2) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const int l = lg + NW * j;
-            const double2 t = tw[(l * n) & (T128 - 1)];
-            acc[j].x = fma(x, t.x, acc[j].x);
-            acc[j].y = fma(x, t.y, acc[j].y);
+            const int l = min(lg + NW * j, H128);         // rows beyond 64 are not stored
+            const double2 t = tw[(l * n2) & (T128 - 1)];
+            const double2 y = spec[(n2 * 16 + (l & 15)) * 64 + m];
+            acc[j].x = fma(t.x, y.x, fma(-t.y, y.y, acc[j].x));
+            acc[j].y = fma(t.x, y.y, fma(t.y, y.x, acc[j].y));
         }
     }
-    __syncthreads();                                        // staging consumed
+    __syncthreads();                                        // Y consumed
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int l = lg + NW * j;
