@@ -375,11 +375,16 @@ __global__ __launch_bounds__(64 * kGroup, 2) void fofse_bwd_group_kernel(BParams
         for (int r = 0; r < kRC; ++r) {
             const int nu = lane + 64 * r;
             const bool valid = present && nu < K;
-            // loaded unconditionally (index clamped into the block's record) so
-            // that the loads of every row are in flight together
-            const size_t ri = (size_t)bj * K + min(nu, K - 1);
-            const int key_l = p.sel[ri];
-            const double2 c_l = make_double2(p.coef[2 * ri], p.coef[2 * ri + 1]);
+            // loaded without a per-row branch (index clamped into the block's
+            // record; an empty record, K = 0, is never read) so that the loads
+            // of every row are in flight together
+            int key_l = 0;
+            double2 c_l = make_double2(0.0, 0.0);
+            if (K > 0) {
+                const size_t ri = (size_t)bj * K + min(nu, K - 1);
+                key_l = p.sel[ri];
+                c_l = make_double2(p.coef[2 * ri], p.coef[2 * ri + 1]);
+            }
             const int key = valid ? key_l & (T * T - 1) : 0;
             double2 c = valid ? c_l : make_double2(0.0, 0.0);
             R.x[r] = pack_class(key >> 6, key & 63);

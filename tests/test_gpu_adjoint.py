@@ -236,3 +236,36 @@ def test_autograd_mse_loss(frame_areas):
     np.testing.assert_allclose(rg.grad.cpu().numpy(), [rb.sum(), gmb.sum()], rtol=1e-5)
     print(f"[gpu] autograd: {n} blocks ({int(div.sum())} diverging from the oracle's selection), "
           f"max rel dL/df {np.max(err / scale):.2e}", flush=True)
+
+
+@pytest.mark.parametrize("T,side,path", [(64, 48, "grouped"), (64, 48, "split"), (32, 24, "split"),
+                                         (16, 12, "split"), (128, 64, "auto")])
+def test_backward_empty_record(T, side, path):
+    """K = 0: the model is 0, so every gradient is 0.  The record pointers are
+    valid but hold no iteration; no organisation may read them."""
+    from paper_2207_01205_amd import fofse as F
+    rng = np.random.default_rng(T + side)
+    target = np.zeros((side, side), np.uint8)
+    target[side // 3:2 * side // 3, side // 3:2 * side // 3] = 1
+    n = 40
+    areas = (100 + 20 * rng.normal(size=(n, side, side))).astype(np.float32)
+    plan = _plan(side, side, T, 0, target)
+    if path == "grouped":
+        plan.set_path(F.FOFSE_PATH_GROUPED)
+    elif path == "split":
+        plan.set_path(F.FOFSE_PATH_SPLIT)
+    print(f"[gpu] backward K = 0: T={T} {side}x{side} {path}", flush=True)
+    dev = torch.device("cuda", 0)
+    a = torch.from_numpy(areas).to(dev)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    sel = torch.zeros(1, dtype=torch.int32, device=dev)
+    cf = torch.zeros(2, dtype=torch.float64, device=dev)
+    go = torch.from_numpy(rng.normal(size=(n, plan.nB)).astype(np.float32)).to(dev)
+    ga = torch.full((n, side, side), 7.0, dtype=torch.float32, device=dev)
+    grg = torch.zeros(2, dtype=torch.float64, device=dev)
+    gb = torch.full((n, 2), 7.0, dtype=torch.float64, device=dev)
+    F.fofse_backward(plan.handle, n, a.data_ptr(), 0, rg.data_ptr(), sel.data_ptr(), cf.data_ptr(), go.data_ptr(),
+                     ga.data_ptr(), grg.data_ptr(), gb.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    torch.cuda.synchronize()
+    assert np.all(ga.cpu().numpy() == 0.0)
+    assert np.all(grg.cpu().numpy() == 0.0) and np.all(gb.cpu().numpy() == 0.0)
