@@ -397,7 +397,7 @@ __device__ __forceinline__ void process_item(GroupShared<T>& sh, const KParams& 
     // the thread index as an opaque per-item value: keeps the compiler from
     // hoisting every per-thread sample address of the item's loops out of the
     // item loop (they would be spilled for the whole kernel and reloaded per item)
-    asm volatile("" : "+v"(tid));
+    asm volatile("" : "+v"(tid), "+v"(lane));
     __syncthreads();                       // previous item done with LDS
     if (tid < kGroup) sh.flags[tid] = params_ok ? 0 : FOFSE_BLOCK_BAD_PARAM;
     if (tid == 0) sh.asym = 0;
