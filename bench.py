@@ -43,8 +43,8 @@ FP32_VECTOR_PEAK = 157.3e12    # published packed-FP32 vector peak
 # scaled by 2.0 and WRITE_SIZE by 1.0.  The figure holds only for the kernel
 # sources it was taken on (hash below); otherwise the bench reports null.
 KERNEL_SOURCES = ("fofse_group.hip", "iterate.hpp", "device_common.hpp", "fofse_kernel.h")
-TRAFFIC = {"sources_sha256_16": "ac78dddef6439972", "blocks": 12864,
-           "fetch_kib": 91541.6, "write_kib": 86537.8, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "ea4327c021b01fac", "blocks": 12864,
+           "fetch_kib": 67352.2, "write_kib": 67331.1, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # FP64 instruction counters of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU_FMA_F64
@@ -52,7 +52,7 @@ TRAFFIC = {"sources_sha256_16": "ac78dddef6439972", "blocks": 12864,
 # --steps 2 --warmup 0 --no-cpu-baseline --no-single-frame --mixed 2048 --tune 0
 # --jobs 1``), per dispatch on the same batch: FMA 434,005,852, ADD 213,030,048,
 # MUL 102,321,940 wave instructions.
-COUNTERS = {"sources_sha256_16": "ac78dddef6439972", "blocks": 12864, "flop": 75735276288.0}
+COUNTERS = {"sources_sha256_16": "ea4327c021b01fac", "blocks": 12864, "flop": 75735276288.0}
 
 
 def measured_traffic(n_blocks: int):
