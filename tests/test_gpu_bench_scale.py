@@ -1,0 +1,72 @@
+"""The bench's forward workload at its full size and in its launch
+configuration, checked against the FP64 oracle on seeded samples: 16
+synthetic 1080p frames with 10% of the 16 x 16 macroblocks lost (12,864
+blocks, 48 x 48 areas, T = 64, K = 200, rho_hat = 0.8, gamma = 0.5), one launch
+on the default organisation (the grouped kernel at this size).
+
+Forward: the sampled blocks follow the selection rule and the output bar of
+the other parity tests.  Adjoint: one launch over the whole batch with the
+GPU's own record; the sampled blocks' dL/df and (rho_hat, gamma) gradients
+match the oracle adjoint of the same record (the adjoint is defined for any
+fixed selection) to the bars of the adjoint tests.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2207_01205_amd import synth
+from test_gpu_adjoint import TOL, oracle_adjoints
+from test_gpu_parity import _plan, check_parity, oracle_on, run_gpu
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bench_batch():
+    parts = [synth.frame_concealment(i, 1000 + i) for i in range(16)]
+    areas = np.concatenate([p.areas for p in parts])
+    known = np.concatenate([p.known for p in parts])
+    return areas, known, parts[0].target
+
+
+def test_bench_batch_forward_sampled(bench_batch):
+    areas, known, target = bench_batch
+    assert areas.shape == (12864, 48, 48)
+    plan = _plan(48, 48, 64, 200, target)
+    out, sel, coef, st = run_gpu(plan, areas, known, 0.8, 0.5, "bench batch, 12,864 blocks")
+    assert np.all(st == 0) and np.all(np.isfinite(out))
+    idx = np.sort(np.random.default_rng(13).choice(len(areas), 40, replace=False))
+    ref = oracle_on(areas[idx], known[idx], target, 64, 0.8, 0.5, 200)
+    check_parity(ref, target, out[idx], sel[idx], coef[idx], st[idx], "bench batch sample")
+
+
+def test_bench_batch_adjoint_sampled(bench_batch):
+    areas, known, target = bench_batch
+    n = areas.shape[0]
+    plan = _plan(48, 48, 64, 200, target)
+    dev = torch.device("cuda", 0)
+    a = torch.from_numpy(areas).to(dev)
+    k = torch.from_numpy(known).to(dev)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    print("[gpu] bench batch adjoint, 12,864 blocks", flush=True)
+    _, sel, coef, st = plan.extrapolate(a, rg, known=k, record=True)
+    rng = np.random.default_rng(17)
+    gbar = rng.normal(size=(n, plan.nB)).astype(np.float32)
+    go = torch.from_numpy(gbar).to(dev)
+    ga, grg, gb = plan.backward(a, rg, sel, coef, go, known=k, per_block=True)
+    torch.cuda.synchronize()
+    assert torch.all(st == 0)
+    ga, gb, sel = ga.cpu().numpy(), gb.cpu().numpy(), sel.cpu().numpy()
+    assert np.all(np.isfinite(ga)) and np.all(np.isfinite(gb))
+    np.testing.assert_allclose(grg.cpu().numpy(), gb.sum(axis=0), rtol=1e-12)
+    idx = np.sort(rng.choice(n, 12, replace=False))
+    f = areas[idx].astype(np.float64)
+    kn = known[idx] * (1 - target)[None]
+    fb, rb, gmb = oracle_adjoints(f, kn, target, 64, 0.8, 0.5, sel[idx], gbar[idx])
+    scale = np.abs(fb).reshape(len(idx), -1).max(axis=1)
+    err = np.abs(ga[idx] - fb).reshape(len(idx), -1).max(axis=1)
+    assert np.all(err <= TOL * scale + 1e-12), np.max(err / scale)
+    np.testing.assert_allclose(gb[idx, 0], rb, rtol=TOL, atol=TOL * np.abs(rb).max() * 1e-3)
+    np.testing.assert_allclose(gb[idx, 1], gmb, rtol=TOL, atol=TOL * np.abs(gmb).max() * 1e-3)
+    print(f"[gpu] bench batch adjoint sample: max rel dL/df {np.max(err / scale):.2e}", flush=True)
