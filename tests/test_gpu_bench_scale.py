@@ -70,3 +70,55 @@ def test_bench_batch_adjoint_sampled(bench_batch):
     np.testing.assert_allclose(gb[idx, 0], rb, rtol=TOL, atol=TOL * np.abs(rb).max() * 1e-3)
     np.testing.assert_allclose(gb[idx, 1], gmb, rtol=TOL, atol=TOL * np.abs(gmb).max() * 1e-3)
     print(f"[gpu] bench batch adjoint sample: max rel dL/df {np.max(err / scale):.2e}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mixed_batch():
+    """The bench's mixed-size batch at full size: 25,000 blocks of each class
+    (4x4, 8x8, 16x16 and 32x32 losses at seeded positions of four synthetic
+    1080p frames, seeded order within each class)."""
+    imgs = [synth.frame(100 + i) for i in range(4)]
+    classes = []
+    for ci, (block, support, T, K) in enumerate(synth.MIXED_CLASSES):
+        parts = [synth.mixed_blocks(img, 1000 * ci + j, block, support, 25000 // 4) for j, img in enumerate(imgs)]
+        areas = np.concatenate([q[0] for q in parts])
+        order = np.random.default_rng(ci).permutation(len(areas))
+        classes.append((block, T, K, np.ascontiguousarray(areas[order]), parts[0][1]))
+    return classes
+
+
+def test_mixed_batch_full_size_sampled(mixed_batch):
+    """Every class of the mixed batch in one launch each on its default
+    organisation; two seeded blocks per class against the oracle forward and
+    one against the oracle adjoint of the GPU's own record."""
+    dev = torch.device("cuda", 0)
+    rg = torch.tensor([0.8, 0.5], dtype=torch.float64, device=dev)
+    for ci, (block, T, K, areas, target) in enumerate(mixed_batch):
+        n, A = areas.shape[0], areas.shape[1]
+        assert n == 25000
+        plan = _plan(A, A, T, K, target)
+        out, sel, coef, st = run_gpu(plan, areas, None, 0.8, 0.5, f"mixed {block}x{block} T={T} full class")
+        assert np.all(st == 0) and np.all(np.isfinite(out))
+        rng = np.random.default_rng(100 + ci)
+        idx = np.sort(rng.choice(n, 2, replace=False))
+        ref = oracle_on(areas[idx], None, target, T, 0.8, 0.5, K)
+        check_parity(ref, target, out[idx], sel[idx], coef[idx], st[idx], f"mixed {block}x{block} sample")
+        a = torch.from_numpy(areas).to(dev)
+        gbar = rng.normal(size=(n, plan.nB)).astype(np.float32)
+        s_t = torch.from_numpy(np.ascontiguousarray(sel)).to(dev)
+        c_t = torch.from_numpy(np.ascontiguousarray(coef)).to(dev)
+        ga, grg, gb = plan.backward(a, rg, s_t, c_t, torch.from_numpy(gbar).to(dev), per_block=True)
+        torch.cuda.synchronize()
+        ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+        assert np.all(np.isfinite(ga)) and np.all(np.isfinite(gb))
+        j = idx[:1]
+        kn = np.broadcast_to(1 - target, (1,) + target.shape).astype(np.uint8)
+        fb, rb, gmb = oracle_adjoints(areas[j].astype(np.float64), kn, target, T, 0.8, 0.5, sel[j], gbar[j])
+        scale = np.abs(fb).max()
+        assert np.abs(ga[j] - fb).max() <= TOL * scale + 1e-12
+        # a sampled block's gradient can be near 0 by cancellation: the absolute
+        # bar is TOL of the largest gradient of the class
+        np.testing.assert_allclose(gb[j, 0], rb, rtol=TOL, atol=TOL * np.abs(gb[:, 0]).max())
+        np.testing.assert_allclose(gb[j, 1], gmb, rtol=TOL, atol=TOL * np.abs(gb[:, 1]).max())
+        print(f"[gpu] mixed {block}x{block}: adjoint sample rel dL/df {np.abs(ga[j] - fb).max() / scale:.2e}",
+              flush=True)
