@@ -122,3 +122,25 @@ def test_mixed_batch_full_size_sampled(mixed_batch):
         np.testing.assert_allclose(gb[j, 1], gmb, rtol=TOL, atol=TOL * np.abs(gb[:, 1]).max())
         print(f"[gpu] mixed {block}x{block}: adjoint sample rel dL/df {np.abs(ga[j] - fb).max() / scale:.2e}",
               flush=True)
+
+
+def test_bench_batch_dct_and_full_compensation_sampled(bench_batch):
+    """The bench's DCT-basis and full-compensation legs: the same 12,864-block
+    batch in one launch each, sampled against the DCT oracle and the OFSE
+    oracle (eqs. 10-13)."""
+    import test_gpu_dct as D
+    import test_gpu_ofse as O
+    areas, known, target = bench_batch
+    rng = np.random.default_rng(19)
+    plan = D._plan(48, 48, 200, target)
+    out, sel, coef, st = D.run_gpu(plan, areas, known, 0.8, 0.5, "bench batch, DCT basis")
+    assert np.all(st == 0) and np.all(np.isfinite(out))
+    idx = np.sort(rng.choice(len(areas), 6, replace=False))
+    ref = D.oracle_on(areas[idx], known[idx], target, 64, 0.8, 0.5, 200)
+    D.check_parity(ref, target, out[idx], sel[idx], coef[idx], st[idx], "bench batch DCT sample")
+    plan = O._plan(48, 48, 200, target)
+    out, sel, coef, st = O.run_gpu(plan, areas, known, 0.8, 0.5, "bench batch, full compensation")
+    assert np.all(st == 0) and np.all(np.isfinite(out))
+    idx = np.sort(rng.choice(len(areas), 4, replace=False))
+    ref = O.oracle_on(areas[idx], known[idx], target, 0.8, 200)
+    O.check_parity(ref, target, out[idx], sel[idx], coef[idx], st[idx], "bench batch full compensation sample")
