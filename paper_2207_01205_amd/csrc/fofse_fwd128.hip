@@ -286,13 +286,15 @@ __device__ __forceinline__ void run_wave128(RowRegs<row_begin128<NW>(WI + 1) - r
         int wslot = (int)(127 - (mlo & 127u)) - k0;
         wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
         const bool whalf = ((mlo >> 7) & 1u) == 0u;
-        const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
+        // the winner's value, read from its column half only (a uniform branch)
+        double2 wvh;
+        if (whalf) wvh = R1.fetch(wslot, wl);
+        else wvh = R0.fetch(wslot, wl);
         Xchg<NW>& x = xchg[it & 1];
         if (lane == 0) {
             x.hi[WI] = mhi;
             x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
-            const double vx = whalf ? wv1.x : wv0.x, vy = whalf ? wv1.y : wv0.y;
-            x.val[WI] = make_double2(vx, vy);
+            x.val[WI] = wvh;
         }
         __syncthreads();
         uint32_t chi[NW], clo[NW];
@@ -531,13 +533,15 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
         int wslot = (int)(127 - (mlo & 127u)) - k0;
         wslot = __builtin_amdgcn_readfirstlane(wslot < 0 ? 0 : (wslot >= S ? S - 1 : wslot));
         const bool whalf = ((mlo >> 7) & 1u) == 0u;
-        const double2 wv0 = R0.fetch(wslot, wl), wv1 = R1.fetch(wslot, wl);
+        // the winner's value, read from its column half only (a uniform branch)
+        double2 wvh;
+        if (whalf) wvh = R1.fetch(wslot, wl);
+        else wvh = R0.fetch(wslot, wl);
         Xchg<NW>& x = xchg[it & 1];
         if (lane == 0) {
             x.hi[WI] = mhi;
             x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
-            const double vx = whalf ? wv1.x : wv0.x, vy = whalf ? wv1.y : wv0.y;
-            x.val[WI] = make_double2(vx, vy);
+            x.val[WI] = wvh;
         }
         __syncthreads();
         uint32_t chi[NW], clo[NW];
