@@ -797,7 +797,11 @@ __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128
     __shared__ Shared128G sh;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     const int lane = tid & 63, wave = tid >> 6;
-    const int jb = wave / kWaves128G, wi = wave % kWaves128G;
+    // wave WI of a block holds rows row_begin128(WI)..: 17, 16, 16, 16.  The
+    // second block's row ranges are rotated by one wave so that the two
+    // 17-row waves do not share a SIMD (the waves of a workgroup are spread
+    // over the SIMDs in turn; the barrier waits for the busiest SIMD)
+    const int jb = wave / kWaves128G, wi = (wave + jb) % kWaves128G;
     const double rho = p.rho_gamma[0], gamma = p.rho_gamma[1];
     const bool params_ok = param_ok(rho) && param_ok(gamma);
     for (int i = tid; i < T128; i += NT) sh.tw[i] = p.twiddle[i];
