@@ -427,18 +427,48 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
     constexpr int r2m = k0 + S - 1;                       // V2 mirrored: k > Q
     int u = 0, v = 0;
     double ca = 0.0, cb = 0.0;
+    // window rows: W1 direct a = k - u, mirrored u - k; W2 direct k + u,
+    // mirrored 128 - k - u (window row = a + 32).  Each read form has one
+    // base per column half at the wave's slot of lowest row (the smallest k
+    // for a direct form, the largest for a mirrored one), so that every
+    // slot reads at a compile-time offset above it.
+    const double* bs1d[2], *bs1m[2], *bs2d[2], *bs2m[2];
+    auto set_bases = [&](int uu, int vv) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = lane + 64 * h;
+            bs1d[h] = vw + (r1d - uu + Q) * T128 + ((c - vv) & (T128 - 1));
+            bs1m[h] = vw + (uu - r1m + Q) * T128 + ((vv - c) & (T128 - 1));
+            bs2d[h] = vw + (r2d + uu + Q) * T128 + ((c + vv) & (T128 - 1));
+            bs2m[h] = vw + (T128 - r2m - uu + Q) * T128 + ((-c - vv) & (T128 - 1));
+        }
+    };
+    auto rd = [&](int k, int h, double& V1, double& V2) {
+        V1 = k >= Q ? bs1d[h][(k - r1d) * T128] : bs1m[h][(r1m - k) * T128];
+        V2 = k <= Q ? bs2d[h][(k - r2d) * T128] : bs2m[h][(r2m - k) * T128];
+    };
+    constexpr int CH = 2;
+    constexpr int NC = (S + CH - 1) / CH;
+    double xv[2][CH][2][2];                      // [buffer][slot][half][V1, V2]
+    auto load = [&](int q, int bf) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int s = q * CH + j;
+            if (s < S) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) rd(k0 + s, h, xv[bf][j][h][0], xv[bf][j][h][1]);
+            }
+        }
+    };
+    set_bases(0, 0);
+    load(0, 0);
     for (int it = 0; it < K; ++it) {
-        // per column half h (column c = lane + 64 h): column indices of the
-        // four read forms and the signs of their wraps
-        int col[2][4];
+        // per column half h (column c = lane + 64 h): the signs of the wraps
+        // of the four read forms
         double A1d[2], B1d[2], A1m[2], B1m[2], A2d[2], B2d[2], A2m[2], B2m[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int c = lane + 64 * h;
-            col[h][0] = (c - v) & (T128 - 1);
-            col[h][1] = (v - c) & (T128 - 1);
-            col[h][2] = (c + v) & (T128 - 1);
-            col[h][3] = (-c - v) & (T128 - 1);
             const bool n1d = odd_c && c < v;
             const bool n1m = odd_c && c > v;
             const bool n2d = odd_c && c + v >= T128;
@@ -448,37 +478,6 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
             A2d[h] = n2d ? ca : -ca; B2d[h] = n2d ? -cb : cb;
             A2m[h] = n2m ? ca : -ca; B2m[h] = n2m ? -cb : cb;
         }
-        // window rows: W1 direct a = k - u, mirrored u - k; W2 direct k + u,
-        // mirrored 128 - k - u (window row = a + 32).  Each read form has one
-        // base per column half at the wave's slot of lowest row (the smallest k
-        // for a direct form, the largest for a mirrored one), so that every
-        // slot reads at a compile-time offset above it.
-        const double* bs1d[2], *bs1m[2], *bs2d[2], *bs2m[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            bs1d[h] = vw + (r1d - u + Q) * T128 + col[h][0];
-            bs1m[h] = vw + (u - r1m + Q) * T128 + col[h][1];
-            bs2d[h] = vw + (r2d + u + Q) * T128 + col[h][2];
-            bs2m[h] = vw + (T128 - r2m - u + Q) * T128 + col[h][3];
-        }
-        auto rd = [&](int k, int h, double& V1, double& V2) {
-            V1 = k >= Q ? bs1d[h][(k - r1d) * T128] : bs1m[h][(r1m - k) * T128];
-            V2 = k <= Q ? bs2d[h][(k - r2d) * T128] : bs2m[h][(r2m - k) * T128];
-        };
-        constexpr int CH = 2;
-        constexpr int NC = (S + CH - 1) / CH;
-        double xv[2][CH][2][2];                  // [buffer][slot][half][V1, V2]
-        auto load = [&](int q, int bf) {
-#pragma unroll
-            for (int j = 0; j < CH; ++j) {
-                const int s = q * CH + j;
-                if (s < S) {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) rd(k0 + s, h, xv[bf][j][h][0], xv[bf][j][h][1]);
-                }
-            }
-        };
-        load(0, 0);
         double best = 0.0;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -562,6 +561,9 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
         u = 127 - (int)(wlo & 127u);
         u = u > H128 ? H128 : u;
         v = (63 - (int)((wlo >> 7) & 63u)) + (((wlo >> 13) & 1u) ? 0 : 64);
+        // the next iteration's first table reads go out ahead of the coefficient
+        set_bases(u, v);
+        load(0, 0);
         // eqs. 5, 14 in the rotated frame: ct = gamma Rt[u] / W0, c = ct P(u);
         // a self-conjugate class keeps Re c
         const bool selfc = (u == 0 || u == H128) && (v == 0 || v == H128);
