@@ -462,6 +462,14 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
     };
     set_bases(0, 0);
     load(0, 0);
+    // the block's maximum key, taken by LDS atomics into one of three 64-bit
+    // slots (the first words of xchg[0]): slot it % 3 collects iteration it,
+    // and slot (it + 1) % 3, last read before the previous barrier, is cleared
+    // for the next iteration
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(&xchg[0].hi[0]);
+    if (WI == 0 && lane == 0) keys[0] = 0ull;
+    __syncthreads();
+    int ks = 0;
     for (int it = 0; it < K; ++it) {
         // per column half h (column c = lane + 64 h): the signs of the wraps
         // of the four read forms
@@ -537,26 +545,21 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
         if (whalf) wvh = R1.fetch(wslot, wl);
         else wvh = R0.fetch(wslot, wl);
         Xchg<NW>& x = xchg[it & 1];
+        const int kn = ks == 2 ? 0 : ks + 1;
         if (lane == 0) {
-            x.hi[WI] = mhi;
-            x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
+            const uint32_t lo = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
+            atomicMax(&keys[ks], ((unsigned long long)mhi << 32) | lo);
             x.val[WI] = wvh;
+            if (WI == 0) keys[kn] = 0ull;
         }
         __syncthreads();
-        uint32_t chi[NW], clo[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+        const uint32_t wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)keys[ks]);
+        ks = kn;
+        // the wave holding the winner's row
+        const int wrow = 127 - (int)(wlo & 127u);
         int bw = 0;
-        uint32_t whi = chi[0], wlo = clo[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
-            bw = gt ? w : bw;
-            whi = gt ? chi[w] : whi;
-            wlo = gt ? clo[w] : wlo;
-        }
-        bw = __builtin_amdgcn_readfirstlane(bw);
-        wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
+        for (int w = 1; w < NW; ++w) bw += wrow >= row_begin128<NW>(w) ? 1 : 0;
         const double2 wv = x.val[bw];            // Rt[u]
         u = 127 - (int)(wlo & 127u);
         u = u > H128 ? H128 : u;
