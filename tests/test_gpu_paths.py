@@ -200,6 +200,24 @@ def test_split_wave_counts(frame_img, T, waves):
           f"split/{waves} T={T} per-block masks", min_same=n // 2)
 
 
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_grouped_128_short_records(frame_img, K):
+    """The grouped T = 128 forward on point-symmetric masks at K = 1, 2, 3.  Its
+    block maximum goes through three 64-bit key slots in turn, each cleared one
+    iteration ahead, and every work item starts from a cleared first slot; 1,200
+    blocks give each workgroup two or three items, so items start after every
+    residue of K mod 3."""
+    block, support, _ = _SPLIT_GEOM[128]
+    n = 1200
+    areas, target, _, _ = synth.mixed_blocks(frame_img, 900 + K, block, support, n)
+    side = areas.shape[1]
+    plan = _plan(side, side, 128, K, target, path="grouped")
+    plan.set_occupancy(1)
+    out, sel, coef, st = run_gpu(plan, areas, None, 0.8, 0.5, f"grouped T=128 K={K}")
+    check(oracle_dft(areas, None, target, 128, 0.8, 0.5, K), target, out, sel, coef, st,
+          f"grouped T=128 K={K}", min_same=n // 2)
+
+
 @pytest.mark.parametrize("T,occ", [(64, 1), (64, 2), (128, 1)])
 def test_grouped_occupancy(frame_img, T, occ):
     """Every grouped-path grid the autotuner can pick (resident workgroups per
