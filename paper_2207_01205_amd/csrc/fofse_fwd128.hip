@@ -521,8 +521,9 @@ __device__ __forceinline__ void run_wave128_sym(RowRegs<row_begin128<NW>(WI + 1)
             }
             if constexpr (NC > 1) __builtin_amdgcn_sched_barrier(0);
         }
-        // wavefront maximum and the exchange between the block's wavefronts (as
-        // run_wave128)
+        // wavefront maximum (as run_wave128); the block's maximum over its
+        // wavefronts by the atomic key slots above, each wave publishing its
+        // winner's value in the exchange record
         const uint32_t bhi = (uint32_t)__double2hiint(best), blo = (uint32_t)__double2loint(best);
         const uint32_t mhi = wave_max_u32(bhi);
         uint64_t hits = __ballot(bhi == mhi);
