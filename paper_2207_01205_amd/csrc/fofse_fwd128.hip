@@ -193,6 +193,18 @@ __device__ __forceinline__ void run_wave128(RowRegs<row_begin128<NW>(WI + 1) - r
     int u = 0, v = 0;
     double cr = 0.0, ci = 0.0;
     const int c0 = lane, c1 = lane + 64;
+    // With eight or more waves per block, the block's maximum key is taken by
+    // 64-bit LDS atomics into one of three slots (the first words of xchg[0]):
+    // slot it % 3 collects iteration it, and slot (it + 1) % 3, last read
+    // before the previous barrier, is cleared for the next iteration.  With
+    // four waves the candidates are compared after the barrier.
+    constexpr bool kAtomicMax = NW >= 8;
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(&xchg[0].hi[0]);
+    if constexpr (kAtomicMax) {
+        if (WI == 0 && lane == 0) keys[0] = 0ull;
+        __syncthreads();
+    }
+    int ks = 0;
     for (int it = 0; it < K; ++it) {
         // column indices of the four read forms for both columns
         const int dA0 = (c0 - v) & (T128 - 1), mA0 = (v - c0) & (T128 - 1);
@@ -291,26 +303,45 @@ __device__ __forceinline__ void run_wave128(RowRegs<row_begin128<NW>(WI + 1) - r
         if (whalf) wvh = R1.fetch(wslot, wl);
         else wvh = R0.fetch(wslot, wl);
         Xchg<NW>& x = xchg[it & 1];
-        if (lane == 0) {
-            x.hi[WI] = mhi;
-            x.lo[WI] = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
-            x.val[WI] = wvh;
-        }
-        __syncthreads();
-        uint32_t chi[NW], clo[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+        const uint32_t mkey = (mlo & 0xFFFFC000u) | (((mlo >> 7) & 1u) << 13) | ((uint32_t)(63 - wl) << 7) | (mlo & 127u);
         int bw = 0;
-        uint32_t whi = chi[0], wlo = clo[0];
+        uint32_t wlo;
+        if constexpr (kAtomicMax) {
+            const int kn = ks == 2 ? 0 : ks + 1;
+            if (lane == 0) {
+                atomicMax(&keys[ks], ((unsigned long long)mhi << 32) | mkey);
+                x.val[WI] = wvh;
+                if (WI == 0) keys[kn] = 0ull;
+            }
+            __syncthreads();
+            wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)keys[ks]);
+            ks = kn;
+            // the wave holding the winner's row
+            const int wrow = 127 - (int)(wlo & 127u);
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
-            bw = gt ? w : bw;
-            whi = gt ? chi[w] : whi;
-            wlo = gt ? clo[w] : wlo;
+            for (int w = 1; w < NW; ++w) bw += wrow >= row_begin128<NW>(w) ? 1 : 0;
+        } else {
+            if (lane == 0) {
+                x.hi[WI] = mhi;
+                x.lo[WI] = mkey;
+                x.val[WI] = wvh;
+            }
+            __syncthreads();
+            uint32_t chi[NW], clo[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { chi[w] = x.hi[w]; clo[w] = x.lo[w]; }
+            uint32_t whi = chi[0];
+            wlo = clo[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                const bool gt = chi[w] > whi || (chi[w] == whi && clo[w] > wlo);
+                bw = gt ? w : bw;
+                whi = gt ? chi[w] : whi;
+                wlo = gt ? clo[w] : wlo;
+            }
+            bw = __builtin_amdgcn_readfirstlane(bw);
+            wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
         }
-        bw = __builtin_amdgcn_readfirstlane(bw);
-        wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wlo);
         const double2 wv = x.val[bw];
         // selected class: grid row u (index l), grid column v (index k)
         u = 127 - (int)(wlo & 127u);
