@@ -143,7 +143,8 @@ int hash_slots(int n) {
 
 // Workspace of the grouped path for a capacity of n blocks: hash table of
 // hsize slots (key 8 B, representative, count, first item: 4 B each), per-block
-// class and position, per-item block list, size and class, three counters.
+// class and position, per-item block list, size and class, the single-mask
+// count and up to twelve counters.
 size_t workspace_bytes_for(int n) {
     return (size_t)hash_slots(n) * 20 + (size_t)n * (8 + 4 * fofse::kGroup + 8) + 64;
 }

@@ -725,13 +725,24 @@ struct Shared128G {
     int next;                           // next work item of the workgroup (queue)
 };
 static_assert(VROWS128 * T128 * sizeof(double) <= ROWS128 * T128 * sizeof(double2), "V window fits the row half");
+static_assert(2 * sizeof(Xchg<kBlocks128G * kWaves128G>) <= sizeof(Shared128G::xchg), "eight-wave records fit");
 
-// One work item as seen by wave WI of block slot jb.  Every wave of the
-// workgroup runs the same sequence of barriers.
-template <int WI>
+// The exchange records of block slot jb: its own pair, or, with eight waves
+// on one block, both slots' pairs as one pair of eight-wave records.
+template <int NW>
+__device__ __forceinline__ Xchg<NW>* xchg_of(Shared128G& sh, int jb) {
+    if constexpr (NW == kWaves128G) return sh.xchg[jb];
+    else return reinterpret_cast<Xchg<NW>*>(&sh.xchg[0][0]);
+}
+
+// One work item as seen by wave WI of block slot jb, NW waves per block: four
+// for an item of two blocks, all eight (jb = 0) for an item of one block.
+// Every wave of the workgroup runs the same sequence of barriers.
+template <int NW, int WI>
 __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const GroupArgs& g, int item, int tid,
                                         int lane, int jb, bool params_ok, double gamma) {
-    constexpr int NW = kWaves128G, NT = kBlocks128G * NW * 64;
+    static_assert(NW == kWaves128G || NW == kBlocks128G * kWaves128G, "four waves per block, or all eight");
+    constexpr int NT = kBlocks128G * kWaves128G * 64;
     constexpr int k0 = row_begin128<NW>(WI);
     constexpr int S = row_begin128<NW>(WI + 1) - k0;
     const int M = p.M, N = p.N, MN = M * N, K = p.K;
@@ -811,10 +822,10 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
                 if (h) R1.set(s, nr, ni); else R0.set(s, nr, ni);
             }
         }
-        run_wave128_sym<NW, WI>(R0, R1, reinterpret_cast<const double*>(sh.spec), sh.ht, sh.xchg[jb], p, bj,
+        run_wave128_sym<NW, WI>(R0, R1, reinterpret_cast<const double*>(sh.spec), sh.ht, xchg_of<NW>(sh, jb), p, bj,
                                 lane, live ? gamma / W0 : 0.0, live);
     } else {
-        run_wave128<NW, WI>(R0, R1, sh.spec, sh.xchg[jb], p, bj, lane, live ? gamma / W0 : 0.0, live);
+        run_wave128<NW, WI>(R0, R1, sh.spec, xchg_of<NW>(sh, jb), p, bj, lane, live ? gamma / W0 : 0.0, live);
     }
     if (present && !live) {                       // empty record: the synthesised model is 0
         for (int it = WI * 64 + lane; it < K; it += NW * 64) {
@@ -828,6 +839,25 @@ __device__ __forceinline__ void item128(Shared128G& sh, const KParams& p, const 
 
 }  // namespace
 
+// Clears the list of lone items and its queue counter before the grouped
+// T = 128 launches.  The grouping's counters are g.counts[0] (grouped items),
+// [1] (all items) and [2] (the first launch's queue); [3] counts the listed
+// lone items and [4] is the second launch's queue (the workspace holds twelve).
+__global__ void k_fwd128_lone_clear(GroupArgs g) {
+    if (__builtin_amdgcn_workitem_id_x() == 0) {
+        g.counts[3] = 0;
+        g.counts[4] = 0;
+    }
+}
+
+// LONE = false: the work items of two blocks, four waves per block.  An item
+// of one block (a mask no other block has, or the last of an odd class) is
+// appended to a list in g.cls (free once the grouping has filled the items)
+// and left to the LONE = true launch, which runs each listed item on all
+// eight waves; the row partition does not change the arithmetic of any class.
+// With every block of one mask (no grouping) the last item of an odd count
+// stays in the first launch.
+template <bool LONE>
 __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128_group_kernel(KParams p,
                                                                                                GroupArgs g) {
     constexpr int NT = kBlocks128G * kWaves128G * 64;
@@ -847,11 +877,40 @@ __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128
     // (every item costs the same), else a queue, since point-symmetric items
     // run a cheaper iteration (the counter zeroed by the grouping; the next
     // index is fetched while the current item runs)
+    static_assert(kWaves128G == 4, "one instance per wave of a block");
+    if constexpr (LONE) {
+        const int n_lone = g.counts[3];
+        if (n_lone == 0) return;                 // uniform: no barrier is left waiting
+        if (tid == 0) sh.next = atomicAdd(&g.counts[4], 1);
+        __syncthreads();
+        int li = sh.next;
+        while (li < n_lone) {
+            int nxt = 0;
+            if (tid == 0) nxt = atomicAdd(&g.counts[4], 1);
+            const int item = g.cls[li];
+            constexpr int W8 = kBlocks128G * kWaves128G;
+            if (wave == 0) item128<W8, 0>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 1) item128<W8, 1>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 2) item128<W8, 2>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 3) item128<W8, 3>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 4) item128<W8, 4>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 5) item128<W8, 5>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else if (wave == 6) item128<W8, 6>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            else item128<W8, 7>(sh, p, g, item, tid, lane, 0, params_ok, gamma);
+            if (tid == 0) sh.next = nxt;        // every read of the last index preceded the item's barriers
+            __syncthreads();
+            li = sh.next;
+        }
+        return;
+    }
+    // work items: contiguous ranges when every block has the same support
+    // (every item costs the same), else a queue, since point-symmetric items
+    // run a cheaper iteration (the counter zeroed by the grouping; the next
+    // index is fetched while the current item runs)
     const int n_items = g.direct ? (p.n_blocks + kBlocks128G - 1) / kBlocks128G : g.counts[1];
     const int per = (n_items + g.n_wg - 1) / g.n_wg;
     const int i0 = (int)__builtin_amdgcn_workgroup_id_x() * per;
     const int i1 = g.direct ? min(n_items, i0 + per) : n_items;
-    static_assert(kWaves128G == 4, "one instance per wave of a block");
     int item = i0;
     if (!g.direct) {
         if (tid == 0) sh.next = atomicAdd(&g.counts[2], 1);
@@ -861,10 +920,16 @@ __global__ __launch_bounds__(kBlocks128G * kWaves128G * 64, 1) void fofse_fwd128
     while (item < i1) {
         int nxt = 0;
         if (!g.direct && tid == 0) nxt = atomicAdd(&g.counts[2], 1);
-        if (wi == 0) item128<0>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
-        else if (wi == 1) item128<1>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
-        else if (wi == 2) item128<2>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
-        else item128<3>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        if (!g.direct && g.item_n[item] == 1) {
+            if (tid == 0) g.cls[atomicAdd(&g.counts[3], 1)] = item;
+            __syncthreads();                     // every thread has read the index before it is replaced
+        } else {
+            constexpr int W4 = kWaves128G;
+            if (wi == 0) item128<W4, 0>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+            else if (wi == 1) item128<W4, 1>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+            else if (wi == 2) item128<W4, 2>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+            else item128<W4, 3>(sh, p, g, item, tid, lane, jb, params_ok, gamma);
+        }
         if (g.direct) {
             ++item;
         } else {
@@ -892,11 +957,22 @@ hipError_t launch_grouped128(const KParams& p, const GroupArgs& g, int n_cu, hip
     int grid = n_cu;
     if (grid > max_items) grid = max_items;
     ga.n_wg = grid;
+    if (!g.direct) {
+        hipLaunchKernelGGL(k_fwd128_lone_clear, dim3(1), dim3(64), 0, stream, ga);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (tm.start && hipEventRecord(tm.start, stream) != hipSuccess) return hipErrorUnknown;
-    hipLaunchKernelGGL(fofse_fwd128_group_kernel, dim3(grid), dim3(kBlocks128G * kWaves128G * 64), 0, stream, p,
-                       ga);
+    hipLaunchKernelGGL(fofse_fwd128_group_kernel<false>, dim3(grid), dim3(kBlocks128G * kWaves128G * 64), 0,
+                       stream, p, ga);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (!g.direct) {
+        hipLaunchKernelGGL(fofse_fwd128_group_kernel<true>, dim3(grid), dim3(kBlocks128G * kWaves128G * 64), 0,
+                           stream, p, ga);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (tm.stop && hipEventRecord(tm.stop, stream) != hipSuccess) return hipErrorUnknown;
     return launch_synthesis(p, stream);
 }
